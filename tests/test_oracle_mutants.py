@@ -1,0 +1,74 @@
+"""Planted-mistake check of the oracle's pins (CPU only).
+
+Each case copies the oracle and the tests into a temporary directory, plants
+one plausible mistake into the copy of ``refine_oracle.c`` (a dropped term, a
+wrong sign or index, a transposed operand, a wrong constant) and runs the
+oracle pins there: at least one pin must fail.  The repository's oracle is
+never modified.
+"""
+import os
+import shutil
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+MUTANTS = [
+    ("eta dropped from the depth term", "P = 1.0 / (z * z + prm->eta);", "P = 1.0 / (z * z);"),
+    ("eta dropped from the covariance term",
+     "(p->sbar2 * (fx * fx + fy * fy) * (z * z + prm->eta))",
+     "(p->sbar2 * (fx * fx + fy * fy) * (z * z))"),
+    ("z^2 dropped from the covariance term", "P = (a + c) * z * z / (", "P = (a + c) / ("),
+    ("Jacobian sign", "-fx * xh / z}", "fx * xh / z}"),
+    ("camera rotation transposed",
+     "T[r][c] = J[r][0] * Rv[0][c] + J[r][1] * Rv[1][c] + J[r][2] * Rv[2][c];",
+     "T[r][c] = J[r][0] * Rv[c][0] + J[r][1] * Rv[c][1] + J[r][2] * Rv[c][2];"),
+    ("opacity not activated", "p->alpha = sigmoid(plane(planes, stride, 10, i));",
+     "p->alpha = plane(planes, stride, 10, i);"),
+    ("luma weight", "0.587 * p->rgb[1]", "0.578 * p->rgb[1]"),
+    ("quaternion sign", "R[0][1] = 2.0 * (x * y - w * z);", "R[0][1] = 2.0 * (x * y + w * z);"),
+    ("opacity ambiguity squared", "sumOpa += p.alpha * (1.0 - p.alpha);", "sumOpa += p.alpha * p.alpha;"),
+    ("eta dropped from anisotropy", "sumGem += smax / (smin + eta);", "sumGem += smax / smin;"),
+    ("eta dropped from lambda~gem", "log(F[3] + prm->eta)", "log(F[3])"),
+    ("2-sigma footprint", "double r = 3.0 * sqrt(lmax);", "double r = 2.0 * sqrt(lmax);"),
+    ("bottom edge tested against W", "if (H - v + r < m) m = H - v + r;", "if (W - v + r < m) m = W - v + r;"),
+    ("near plane ignored", "int near_ok = z > prm->z_near;", "int near_ok = 1;"),
+    ("sum instead of mean over views", "d += lam[k] * (S / nv) * gt[k];", "d += lam[k] * S * gt[k];"),
+    ("mean squared scale from one axis",
+     "p->sbar2 = (p->s[0] * p->s[0] + p->s[1] * p->s[1] + p->s[2] * p->s[2]) / 3.0;",
+     "p->sbar2 = p->s[0] * p->s[0];"),
+    ("colour magnitude squared",
+     "p->gt_col = sqrt(p->rgb[0] * p->rgb[0] + p->rgb[1] * p->rgb[1] + p->rgb[2] * p->rgb[2]);",
+     "p->gt_col = (p->rgb[0] * p->rgb[0] + p->rgb[1] * p->rgb[1] + p->rgb[2] * p->rgb[2]);"),
+    ("tie-break reversed", "return a < b ? -1 : (a > b);", "return a > b ? -1 : (a < b);"),
+    ("clamp limit from H", "double limx = prm->clamp_k * W / (2.0 * fx);",
+     "double limx = prm->clamp_k * H / (2.0 * fx);"),
+    ("no Jacobian clamp", "double xh = clampd(x / z, -limx, limx);", "double xh = x / z;"),
+    ("principal point dropped", "double u = fx * x / z + cx;", "double u = fx * x / z;"),
+    ("subsampling picks the first views", "((int64_t)jv * n_views) / nv", "jv"),
+]
+
+
+@pytest.mark.parametrize("name,before,after", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_planted_mistake_is_caught(tmp_path, name, before, after):
+    dst = tmp_path / "tree"
+    os.makedirs(dst / "paper_2606_09074_amd")
+    shutil.copytree(os.path.join(ROOT, "oracle"), dst / "oracle",
+                    ignore=shutil.ignore_patterns("*.so", "__pycache__"))
+    shutil.copytree(os.path.join(ROOT, "tests"), dst / "tests",
+                    ignore=shutil.ignore_patterns("__pycache__", "test_oracle_mutants.py"))
+    shutil.copy(os.path.join(ROOT, "paper_2606_09074_amd", "synth.py"), dst / "paper_2606_09074_amd")
+    (dst / "paper_2606_09074_amd" / "__init__.py").write_text("")
+    src = dst / "oracle" / "refine_oracle.c"
+    text = src.read_text()
+    assert text.count(before) == 1, "mutation site not found exactly once"
+    src.write_text(text.replace(before, after))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
+                        "-m", "not gpu", "tests/test_oracle_activation_stats.py",
+                        "tests/test_oracle_projection_score.py", "tests/test_oracle_renderer.py",
+                        "tests/test_oracle_select_compact.py"],
+                       cwd=dst, capture_output=True, text=True, timeout=300)
+    assert r.returncode != 0, f"no pin caught the planted mistake: {name}\n{r.stdout[-2000:]}"
+    assert "FAILED" in r.stdout

@@ -1,0 +1,270 @@
+"""Pins of the oracle's per-view terms and scores (CPU only).
+
+Closed forms of Eq. (13)-(17), finite differences of the pinhole projection,
+Gauss-Hermite moments of the projected 3D Gaussian (scipy rotation, not the
+oracle's), gate special cases and invariances of the view mean (Eq. 20).
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy.spatial.transform import Rotation
+
+from tests.helpers import (CLAMP_K, E_COL, E_LNGEM, E_OPA, ETA, SH_C0, Z_NEAR, camera,
+                           planes_from_prims, raw_prim)
+
+
+def P(**kw):
+    import oracle
+    base = dict(eta=ETA, z_near=Z_NEAR, clamp_k=CLAMP_K, e_col=E_COL, e_opa=E_OPA, e_lngem=E_LNGEM)
+    base.update(kw)
+    return oracle.Params(**base)
+
+
+def _wxyz(rot):
+    x, y, z, w = rot.as_quat()
+    return (w, x, y, z)
+
+
+@pytest.mark.parametrize("z", [0.5, 1.0, 3.0, 17.0])
+@pytest.mark.parametrize("f", [300.0, 1100.0])
+def test_on_axis_isotropic_closed_form(oracle_lib, z, f):
+    """Eq. (16): on the optical axis with fx = fy = f, |J|_F^2 = 2 f^2 / z^2;
+    Eq. (17): the projection term is then 1/(z^2 + eta) in both modes."""
+    prim = raw_prim(mu=(0.0, 0.0, z), log_scale=(-3.0, -3.0, -3.0))
+    cam = camera(fx=f, fy=f, cx=160.0, cy=120.0)
+    for mode in (0, 1):
+        g, amb, d = oracle_lib.pair(prim, cam, P(proj_mode=mode))
+        assert g == 1 and amb == 0
+        assert abs(np.sum(d["J"] ** 2) - 2.0 * f * f / (z * z)) <= 1e-12 * 2 * f * f / (z * z)
+        assert abs(d["P"] - 1.0 / (z * z + ETA)) <= 1e-12 / (z * z + ETA)
+        s2 = math.exp(2 * np.float32(-3.0))
+        # isotropic: Sigma' = (f s / z)^2 I
+        assert abs(d["a"] - (f / z) ** 2 * s2) < 1e-12 * (f / z) ** 2 * s2 * 10
+        assert abs(d["b"]) < 1e-15 * (f / z) ** 2
+        assert abs(d["r"] - 3.0 * f * math.sqrt(s2) / z) < 1e-9 * d["r"]
+
+
+def test_projection_of_a_point(oracle_lib):
+    R = Rotation.from_euler("xyz", [10, -20, 30], degrees=True).as_matrix()
+    t = np.array([0.3, -0.2, 4.0])
+    mu = np.array([0.5, 0.25, -1.0], dtype=np.float32)
+    cam = camera(R=R, t=t, fx=310.0, fy=290.0, cx=150.0, cy=125.0)
+    _, _, d = oracle_lib.pair(raw_prim(mu=mu), cam, P())
+    Rf = cam[:9].astype(np.float64).reshape(3, 3)
+    tf = cam[9:12].astype(np.float64)
+    pc = Rf @ mu.astype(np.float64) + tf
+    np.testing.assert_allclose([d["x"], d["y"], d["z"]], pc, rtol=1e-14)
+    assert abs(d["u"] - (310.0 * pc[0] / pc[2] + 150.0)) < 1e-10
+    assert abs(d["v"] - (290.0 * pc[1] / pc[2] + 125.0)) < 1e-10
+
+
+def test_jacobian_matches_finite_differences_of_projection(oracle_lib):
+    """Eq. (14): J is the derivative of Eq. (13) with respect to the camera-
+    space centre (inside the clamp range)."""
+    fx, fy, cx, cy = 300.0, 280.0, 160.0, 120.0
+    cam = camera(fx=fx, fy=fy, cx=cx, cy=cy)
+
+    def proj(p):
+        return np.array([fx * p[0] / p[2] + cx, fy * p[1] / p[2] + cy])
+
+    for p in ([0.3, -0.2, 2.0], [-0.7, 0.4, 3.5], [0.0, 0.0, 1.0]):
+        p = np.array(p, dtype=np.float32).astype(np.float64)
+        _, _, d = oracle_lib.pair(raw_prim(mu=p), cam, P())
+        h = 1e-6
+        Jfd = np.stack([(proj(p + h * e) - proj(p - h * e)) / (2 * h) for e in np.eye(3)], axis=1)
+        np.testing.assert_allclose(d["J"], Jfd, rtol=1e-7, atol=1e-6)
+
+
+def test_jacobian_clamped_outside_fov(oracle_lib):
+    W, fx = 320, 300.0
+    cam = camera(fx=fx, fy=fx, W=W, H=240)
+    z = 2.0
+    x = float(np.float32(5.0 * z * W / (2 * fx)))   # far to the right of the image
+    _, _, d = oracle_lib.pair(raw_prim(mu=(x, 0.0, z)), cam, P())
+    limx = CLAMP_K * W / (2 * fx)
+    assert abs(d["J"][0, 2] - (-fx * limx / z)) < 1e-9
+    assert abs(d["u"] - (fx * x / z + 160.0)) < 1e-6   # the centre itself is not clamped
+
+
+def _gauss_hermite_projected_cov(mu, Rot, s, cam, n=24):
+    """Second moments of Pi(X), X ~ N(mu, Rot diag(s^2) Rot^T), by tensor
+    Gauss-Hermite quadrature, pushed through the pinhole projection."""
+    x, w = np.polynomial.hermite_e.hermegauss(n)
+    w = w / w.sum()
+    gx, gy, gz = np.meshgrid(x, x, x, indexing="ij")
+    ww = (w[:, None, None] * w[None, :, None] * w[None, None, :]).reshape(-1)
+    std = np.stack([gx.reshape(-1), gy.reshape(-1), gz.reshape(-1)])
+    pts = mu[:, None] + Rot @ (s[:, None] * std)
+    Rv = cam[:9].astype(np.float64).reshape(3, 3)
+    tv = cam[9:12].astype(np.float64)
+    pc = Rv @ pts + tv[:, None]
+    uv = np.stack([cam[12] * pc[0] / pc[2] + cam[14], cam[13] * pc[1] / pc[2] + cam[15]])
+    m = (uv * ww).sum(1)
+    dv = uv - m[:, None]
+    return (dv * ww) @ dv.T
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_projected_covariance_matches_moments(oracle_lib, seed):
+    """Sigma' = J W Sigma W^T J^T equals, to first order in scale/depth, the
+    covariance of the projected 3D Gaussian (EWA local affine approximation)."""
+    rng = np.random.default_rng(seed)
+    rot = Rotation.random(random_state=seed)
+    ls = rng.uniform(-5.5, -3.5, size=3).astype(np.float32)
+    mu = rng.uniform(-0.5, 0.5, size=3).astype(np.float32)
+    camR = Rotation.random(random_state=100 + seed).as_matrix()
+    eye = camR.T @ np.array([0.0, 0.0, -4.0])         # 4 units behind the origin along its view axis
+    t = -camR @ eye
+    cam = camera(R=camR, t=t, fx=900.0, fy=800.0, cx=160.0, cy=120.0)
+    q = _wxyz(rot)
+    _, _, d = oracle_lib.pair(raw_prim(mu=mu, log_scale=ls, quat=q), cam, P())
+    S = np.array([[d["a"], d["b"]], [d["b"], d["c"]]])
+    # reference uses the float32-rounded inputs the oracle sees
+    Rq = Rotation.from_quat(np.array([q[1], q[2], q[3], q[0]], dtype=np.float32)).as_matrix()
+    ref = _gauss_hermite_projected_cov(mu.astype(np.float64), Rq, np.exp(ls.astype(np.float64)), cam)
+    np.testing.assert_allclose(S, ref, rtol=2e-3, atol=2e-3 * np.abs(ref).max())
+
+
+def test_gate_special_cases(oracle_lib):
+    cam = camera()
+    prm = P()
+    # behind the camera, at the near plane, far off-image: invisible
+    assert oracle_lib.pair(raw_prim(mu=(0, 0, -3.0)), cam, prm)[0] == 0
+    assert oracle_lib.pair(raw_prim(mu=(0, 0, 0.1)), cam, prm)[0] == 0
+    assert oracle_lib.pair(raw_prim(mu=(40.0, 0, 3.0)), cam, prm)[0] == 0
+    assert oracle_lib.pair(raw_prim(mu=(0, 0, 3.0)), cam, prm)[0] == 1
+    # a centre off the image still counts while the 3-sigma footprint overlaps:
+    # isotropic s at (x, 0, z) has Sigma' = s^2 J J^T, so r = 3 s f sqrt(1 + (x/z)^2) / z
+    from scipy.optimize import brentq
+    s = math.exp(float(np.float32(math.log(0.05))))
+    z, f = 2.0, 300.0
+
+    def left_margin(x):           # u + r, positive while the footprint reaches x = 0
+        return f * x / z + 160.0 + 3.0 * s * f * math.sqrt(1.0 + (x / z) ** 2) / z
+
+    def bottom_margin(y):         # H - v + r
+        return 240.0 - (f * y / z + 120.0) + 3.0 * s * f * math.sqrt(1.0 + (y / z) ** 2) / z
+
+    for target, expect in ((1.0, 1), (-1.0, 0)):
+        x = brentq(lambda x: left_margin(x) - target, -1.3, -0.5)
+        g, _, d = oracle_lib.pair(raw_prim(mu=(x, 0, z), log_scale=(math.log(0.05),) * 3), cam, prm)
+        assert g == expect, (target, d["u"], d["r"])
+        assert abs(d["u"] + d["r"] - target) < 1e-3
+        y = brentq(lambda y: bottom_margin(y) - target, 0.5, 1.1)
+        g, _, d = oracle_lib.pair(raw_prim(mu=(0, y, z), log_scale=(math.log(0.05),) * 3), cam, prm)
+        assert g == expect, (target, d["v"], d["r"])
+        assert abs(240.0 - d["v"] + d["r"] - target) < 1e-3
+
+
+def test_single_view_score_closed_form(oracle_lib):
+    """Eq. (20) with one view then Eq. (7): D = alpha K / (z^2 + eta) for an
+    isotropic primitive on the axis (any lambda)."""
+    z, ls, logit, dc = 2.5, -3.2, 0.7, (0.1, -0.2, 0.3)
+    prim = raw_prim(mu=(0, 0, z), log_scale=(ls,) * 3, logit=logit, dc=dc)
+    lam = np.array([0.2, 0.5, 0.3])
+    alpha = 1.0 / (1.0 + math.exp(-float(np.float32(logit))))
+    s = math.exp(float(np.float32(ls)))
+    rgb = 0.5 + SH_C0 * np.array(dc, dtype=np.float32).astype(np.float64)
+    K = lam[0] * s * s + lam[1] * np.linalg.norm(rgb) + lam[2] * alpha
+    for mode in (0, 1):
+        D, lo, hi, na = oracle_lib.score(planes_from_prims([prim]), camera()[None], lam, P(proj_mode=mode))
+        ref = alpha * K / (z * z + ETA)
+        assert abs(D[0] - ref) < 1e-12 * ref
+        assert lo[0] == D[0] == hi[0] and na[0] == 0
+
+
+def _scene(n=600, seed=0):
+    from paper_2606_09074_amd import synth
+    spec = synth.SMALL.with_n(n, n_views=12)
+    return synth.make_planes(spec, rng=np.random.default_rng(seed)), synth.make_cameras(spec)
+
+
+LAM = np.array([0.3, 0.35, 0.35])
+
+
+def test_permuting_primitives_permutes_scores(oracle_lib):
+    pl, cams = _scene()
+    D = oracle_lib.score(pl, cams, LAM, P())[0]
+    perm = np.random.default_rng(1).permutation(pl.shape[1])
+    Dp = oracle_lib.score(np.ascontiguousarray(pl[:, perm]), cams, LAM, P())[0]
+    np.testing.assert_array_equal(Dp, D[perm])
+
+
+def test_permuting_and_duplicating_cameras(oracle_lib):
+    pl, cams = _scene()
+    D = oracle_lib.score(pl, cams, LAM, P())[0]
+    perm = np.random.default_rng(2).permutation(cams.shape[0])
+    np.testing.assert_allclose(oracle_lib.score(pl, cams[perm], LAM, P())[0], D, rtol=1e-12, atol=0)
+    dup = np.concatenate([cams, cams, cams])
+    np.testing.assert_allclose(oracle_lib.score(pl, dup, LAM, P())[0], D, rtol=1e-12, atol=0)
+    # subsampling every other view of a doubled rig returns the original rig
+    dbl = np.repeat(cams, 2, axis=0)
+    Ds = oracle_lib.score(pl, dbl, LAM, P(n_sub_views=cams.shape[0]))[0]
+    np.testing.assert_allclose(Ds, D, rtol=1e-12, atol=0)
+
+
+def test_scaling_intrinsics_leaves_scores_unchanged(oracle_lib):
+    pl, cams = _scene()
+    c2 = cams.copy()
+    c2[:, 12:18] *= 2.0               # fx, fy, cx, cy, W, H (exact in float32)
+    for mode in (0, 1):
+        D = oracle_lib.score(pl, cams, LAM, P(proj_mode=mode))[0]
+        np.testing.assert_allclose(oracle_lib.score(pl, c2, LAM, P(proj_mode=mode))[0], D,
+                                   rtol=1e-13, atol=0)
+
+
+def test_rigid_motion_leaves_scores_unchanged(oracle_lib):
+    """Rotating scene and cameras together by 180 degrees about z (exact in
+    float32: sign flips and a quaternion component permutation)."""
+    pl, cams = _scene()
+    D, lo, hi, _ = oracle_lib.score(pl, cams, LAM, P())
+    pl2 = pl.copy()
+    pl2[0] *= -1
+    pl2[1] *= -1
+    w, x, y, z = pl[6], pl[7], pl[8], pl[9]
+    # (0,0,0,1) * (w,x,y,z) = (-z, -y, x, w)
+    pl2[6], pl2[7], pl2[8], pl2[9] = -z, -y, x, w
+    c2 = cams.copy()
+    R = cams[:, :9].reshape(-1, 3, 3).copy()
+    R[:, :, 0] *= -1
+    R[:, :, 1] *= -1
+    c2[:, :9] = R.reshape(-1, 9)
+    D2 = oracle_lib.score(pl2, c2, LAM, P())[0]
+    np.testing.assert_allclose(D2, D, rtol=1e-12, atol=1e-300)
+
+
+def test_translation_invariance_within_rounding(oracle_lib):
+    pl, cams = _scene()
+    D, lo, hi, _ = oracle_lib.score(pl, cams, LAM, P())
+    shift = np.array([0.75, -1.25, 0.5])
+    pl2 = pl.copy()
+    pl2[0:3] = (pl[0:3].astype(np.float64) + shift[:, None]).astype(np.float32)
+    c2 = cams.copy()
+    R = cams[:, :9].astype(np.float64).reshape(-1, 3, 3)
+    c2[:, 9:12] = (cams[:, 9:12].astype(np.float64) - R @ shift).astype(np.float32)
+    D2 = oracle_lib.score(pl2, c2, LAM, P())[0]
+    tol = 1e-5 * np.abs(hi) + 1e-12
+    assert np.all((D2 >= lo - tol) & (D2 <= hi + tol))
+
+
+def test_outside_every_frustum_scores_exactly_zero(oracle_lib):
+    pl, cams = _scene(200)
+    # ring cameras at radius 8 in z = 0 looking inwards; z = 500 is above every frustum
+    pl[2, :50] = 500.0
+    # and behind a single camera placed on the ring looking in
+    D = oracle_lib.score(pl, cams, LAM, P())[0]
+    assert np.all(D[:50] == 0.0)
+    assert np.all(D[50:] >= 0.0) and np.count_nonzero(D[50:]) > 100
+
+
+def test_ablation_switches(oracle_lib):
+    pl, cams = _scene(300)
+    D = oracle_lib.score(pl, cams, LAM, P())[0]
+    Dv = oracle_lib.score(pl, cams, LAM, P(vis_mode=1))[0]
+    alpha = 1.0 / (1.0 + np.exp(-pl[10, :300].astype(np.float64)))
+    np.testing.assert_allclose(Dv * alpha, D, rtol=1e-12, atol=1e-300)
+    # without a projection term every visible view adds alpha: S = (#visible views) alpha
+    D1 = oracle_lib.score(pl, cams, LAM, P(proj_mode=2))[0]
+    Dd = oracle_lib.score(pl, cams, LAM, P(proj_mode=1))[0]
+    assert np.all((D1 > 0) == (D > 0)) and np.all((Dd > 0) == (D > 0))
