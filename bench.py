@@ -1,0 +1,166 @@
+"""Benchmark of one REFINE prune step on one MI355X.
+
+A step is the whole path on one batch: refine_stats -> refine_score ->
+refine_select -> refine_compact, enqueued on one stream, on the medium
+synthetic workload (3M Gaussians x 200 cameras, prune ratio 0.5), inputs
+resident in HBM before timing starts.  Prints ONE JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload medium]
+                  [--no-cpu-baseline]
+
+value = Gaussian-view evaluations per second of the whole step
+(N * |V| / step time); ms_per_step is the time of one 3M-Gaussian prune.
+The roofline object describes refine_score (the dominant launch), timed
+with HIP events on its own stream over the timed region.  cpu_baseline
+times the FP64 CPU oracle on the host's cores on the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# Algorithmic work of the scoring, per (primitive, view) pair and per
+# primitive (FLOP; FMA = 2, mul/add/rcp/sqrt = 1, compares/min/max = 0), and
+# bytes per primitive (14 fp32 attribute planes read, one fp32 score written).
+FLOP_PER_PAIR = {0: 103, 1: 25, 2: 22}
+BYTES_PER_PRIM = 14 * 4 + 4
+PEAK_FP32_TFLOPS = 157.3      # MI355X dense FP32 vector, vendor figure
+PEAK_HBM_GBS = 8000.0
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="medium", choices=["small", "medium", "large"])
+    ap.add_argument("--ratio", type=float, default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU: this build runs the path on a single MI355X "
+              f"(--gpus {args.gpus} requested); the multi-GPU sharding is described in DESIGN.md",
+              file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_2606_09074_amd import _lib, api, synth
+
+    _lib.load()
+    if not torch.cuda.is_available():
+        log("bench.py needs a GPU")
+        return 2
+    spec = synth.SPECS[args.workload]
+    ratio = args.ratio if args.ratio is not None else spec.ratios[0]
+    log(f"bench: generating {spec.name} (n={spec.n}, V={spec.n_views}), ratio {ratio}")
+    planes_np = synth.make_planes(spec)
+    cams_np = synth.make_cameras(spec)
+    n, V = spec.n, cams_np.shape[0]
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    planes = torch.from_numpy(planes_np).to(dev)
+    cams = torch.from_numpy(cams_np).to(dev)
+    params = _lib.default_params()
+    ws = api.workspace(n, V, dev)
+    st = torch.empty(_lib.STATS_BYTES, dtype=torch.uint8, device=dev)
+    scores = torch.empty(n, dtype=torch.float32, device=dev)
+    keep = torch.empty(n, dtype=torch.uint8, device=dev)
+    n_keep = torch.empty(1, dtype=torch.int64, device=dev)
+    cap = n - api.prune_count(n, ratio)
+    out = torch.empty((59, max(cap, 1)), dtype=torch.float32, device=dev)
+    idx = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+    torch.cuda.synchronize()
+
+    phases = ("stats", "score", "select", "compact")
+    n_ev = max(args.steps, 1)
+    ev = {k: [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n_ev)]
+          for k in phases}
+
+    def step(j: int | None):
+        def mark(k, e):
+            if j is not None:
+                ev[k][j][e].record(stream)
+        mark("stats", 0)
+        api.refine_stats(planes, st, ws, params, stream=stream)
+        mark("stats", 1)
+        mark("score", 0)
+        api.refine_score(planes, cams, st, scores, ws, params, stream=stream)
+        mark("score", 1)
+        mark("select", 0)
+        api.refine_select(scores, keep, ws, ratio=ratio, n_keep_out=n_keep, stream=stream)
+        mark("select", 1)
+        mark("compact", 0)
+        api.refine_compact(planes, keep, out, ws, index_map_out=idx, capacity=cap, stream=stream)
+        mark("compact", 1)
+
+    for _ in range(args.warmup):
+        step(None)
+    torch.cuda.synchronize()
+    log(f"bench: warmup done ({args.warmup} steps); timing {args.steps} steps")
+
+    # timed region: wall clock around K steps, HIP events on the launch stream per phase
+    t0 = time.perf_counter()
+    for j in range(args.steps):
+        step(j)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    phase_ms = {k: [a.elapsed_time(b) for a, b in ev[k][:args.steps]] for k in phases}
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    value = n * V / (ms_per_step / 1e3)
+    avg = {k: float(np.mean(v)) for k, v in phase_ms.items()}
+    log(f"bench: {ms_per_step:.3f} ms/step, phases {avg}")
+
+    # refine_score roofline: ALU-bound FP32 work over the event-timed duration
+    flop = FLOP_PER_PAIR[params.proj_mode] * n * V
+    achieved_tflops = flop / (avg["score"] / 1e3) / 1e12
+    roofline = {"bound": "alu", "kernel": "score_views", "achieved": round(achieved_tflops, 3),
+                "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved_tflops / PEAK_FP32_TFLOPS, 4),
+                "traffic": None, "flop_per_pair": FLOP_PER_PAIR[params.proj_mode],
+                "score_ms": round(avg["score"], 4),
+                "hbm_GBs_algorithmic": round(BYTES_PER_PRIM * n / (avg["score"] / 1e3) / 1e9, 1)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        log("bench: timing the FP64 CPU oracle on the same workload")
+        oracle.build(force=False)
+        prm = oracle.Params()
+        tc0 = time.perf_counter()
+        F = oracle.stats(planes_np, eta=prm.eta)
+        lam = oracle.lam(F, prm)
+        D, _, _, _ = oracle.score(planes_np, cams_np, lam, prm)
+        keep_o, _ = oracle.select(D, oracle.n_prune(n, ratio))
+        oracle.compact(planes_np, keep_o)
+        tc = time.perf_counter() - tc0
+        cpu = {"value": round(n * V / tc, 1), "unit": "evals/s", "cores": oracle.num_threads(), "kind": "oracle",
+               "sample": f"full {spec.name} prune (stats+score+select+compact), {tc:.2f} s",
+               "ms_per_prune": round(tc * 1e3, 1)}
+
+    line = {"metric": "Gaussian-view evals/s", "value": round(value, 1), "unit": "evals/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": spec.name, "n": n, "views": V, "ratio": ratio,
+                       "step": "stats+score+select+compact", "ms_per_prune": round(ms_per_step, 4)},
+            "phases_ms": {k: round(v, 4) for k, v in avg.items()},
+            "roofline": roofline, "cpu_baseline": cpu}
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,208 @@
+/*
+ * refine.h -- C ABI of the REFINE importance-scoring and pruning library for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * REFINE (arXiv 2606.09074) scores every Gaussian primitive of a trained 3D
+ * Gaussian Splatting scene without rendering: a diagonal, analytically
+ * approximated Hessian weight per attribute group (Sec. 3.2, Eq. 7-20),
+ * averaged over a set of cameras, is coupled with the primitive's attribute
+ * magnitudes; the bottom beta*N primitives are then removed (Sec. 3.3).
+ *
+ * Conventions shared by every call below:
+ *  - All pointers named d_* and the planes/camera arrays are DEVICE memory,
+ *    allocated and owned by the caller; the library never allocates, frees or
+ *    synchronises.  Every call only enqueues work on `stream` (a hipStream_t;
+ *    NULL = the default stream) and returns.
+ *  - Argument validation happens on the host before any HIP call; a failed
+ *    validation returns REFINE_E_INVALID / REFINE_E_UNSUPPORTED /
+ *    REFINE_E_WORKSPACE and enqueues nothing.  A failed kernel launch returns
+ *    REFINE_E_HIP.  Data-dependent conditions are reported in device memory
+ *    (refine_stats_t.n_nonfinite, the *d_n_out of refine_compact).
+ *  - One workspace of refine_workspace_size(n, n_views) bytes serves every
+ *    call for scenes of up to n primitives and n_views cameras.  Calls that
+ *    share a workspace must be ordered (same stream); calls on different
+ *    streams need different workspaces.
+ *  - No global mutable state: calls are re-entrant across streams.
+ */
+#ifndef REFINE_H
+#define REFINE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    REFINE_OK = 0,
+    REFINE_E_INVALID = -1,      /* a null pointer, negative size, out-of-domain value */
+    REFINE_E_UNSUPPORTED = -2,  /* well-formed but outside what this build handles */
+    REFINE_E_WORKSPACE = -3,    /* workspace missing or smaller than required */
+    REFINE_E_HIP = -4           /* a HIP launch failed */
+} refine_status;
+
+/* Storage type of the scene planes. */
+typedef enum { REFINE_F32 = 0 } refine_dtype;
+
+/* Projection term of the per-view Hessian weight (Eq. 14-17). */
+typedef enum {
+    REFINE_PROJ_COV = 0,    /* Tr(Sigma') z^2 / (sbar^2 (fx^2+fy^2) (z^2+eta)), Sigma' the EWA
+                               projected covariance; equals Eq. 17 on the optical axis */
+    REFINE_PROJ_DEPTH = 1,  /* 1 / (z^2 + eta), Eq. 17 verbatim */
+    REFINE_PROJ_NONE = 2    /* 1 (ablation "w/o P" of Table 3) */
+} refine_proj_mode;
+
+/* Visibility term (Eq. 12 with the zero-occlusion approximation T = 1). */
+typedef enum {
+    REFINE_VIS_ALPHA = 0,   /* V = alpha */
+    REFINE_VIS_NONE = 1     /* V = 1 (ablation "w/o V" of Table 3) */
+} refine_vis_mode;
+
+/*
+ * A scene of n Gaussians stored attribute-major: planes[59][stride] of
+ * `dtype`, plane p of primitive i at planes[p * stride + i].  Planes:
+ *   0..2 centre x,y,z | 3..5 log-scale | 6..9 quaternion w,x,y,z (any norm;
+ *   zero = identity) | 10 opacity logit | 11..13 SH DC r,g,b | 14..58 higher
+ *   SH coefficients.
+ * These are the 59 parameters per primitive of Eq. 1 (Sec. 3.1).
+ * n >= 0, stride >= n, n <= 2^31 - 1.  For an output scene (refine_compact)
+ * n is the capacity in primitives.
+ */
+typedef struct {
+    int64_t n;
+    int64_t stride;
+    int32_t dtype;          /* refine_dtype */
+    int32_t reserved;       /* must be 0 */
+    void* planes;           /* device */
+} refine_scene;
+
+/*
+ * Method constants (defaults from refine_params_default):
+ *  eta      stability constant of Eq. 17, also used in the scene features and
+ *           Eq. 18 (0.05, as in the paper)
+ *  z_near   a view only counts when the centre's depth exceeds this (0.2)
+ *  clamp_k  EWA Jacobian clamp in multiples of the half field of view (1.3)
+ *  e_col, e_opa, e_lngem
+ *           the calibration expectations E[F_col], E[F_opa], E[ln F_gem] of
+ *           Eq. 18 (defaults: expectations under a scene with SH DC ~ N(0,0.5),
+ *           logit ~ N(0,1.5), log-scale ~ N(-4.5,1): 8.892106e-3, 0.1767277,
+ *           -0.4890595)
+ *  proj_mode, vis_mode, equal_lambda
+ *           term switches (refine_proj_mode, refine_vis_mode; equal_lambda = 1
+ *           sets lambda^k = 1/3, the "Equal lambda" row of Table 3)
+ *  n_sub_views
+ *           0 = every camera; m > 0 = cameras floor(j * V / m), j < m (the
+ *           view subsampling of Table B.1 uses m = 64)
+ */
+typedef struct {
+    double eta;
+    double z_near;
+    double clamp_k;
+    double e_col;
+    double e_opa;
+    double e_lngem;
+    int32_t proj_mode;
+    int32_t vis_mode;
+    int32_t equal_lambda;
+    int32_t n_sub_views;
+} refine_params;
+
+/*
+ * Scene statistics written to device memory by refine_stats:
+ *  ybar, f_col, f_opa, f_gem   the features of Eq. (features): mean luma,
+ *                              luma variance, mean alpha(1-alpha), mean
+ *                              max(s)/(min(s)+eta)
+ *  lambda[3]                   {gem, col, opa} weights of Eq. 18-19 (sum 1)
+ *  n                           primitives reduced
+ *  n_nonfinite                 primitives with a non-finite value in one of
+ *                              the 14 planes the scoring reads; when > 0 the
+ *                              features and scores are not meaningful
+ */
+typedef struct {
+    double ybar;
+    double f_col;
+    double f_opa;
+    double f_gem;
+    double lambda[3];
+    int64_t n;
+    int64_t n_nonfinite;
+} refine_stats_t;
+
+/* Library version string (static storage). */
+const char* refine_version(void);
+
+/* Human-readable name of a refine_status (static storage). */
+const char* refine_status_string(int32_t status);
+
+/* Fill *p with the defaults listed above.  No-op on NULL. */
+void refine_params_default(refine_params* p);
+
+/* Number of primitives removed at prune ratio `ratio` in (0, 1): beta*N to
+ * the nearest integer, halves up (Sec. 3.3).  Returns -1 on invalid input. */
+int64_t refine_prune_count(int64_t n, double ratio);
+
+/* Workspace bytes needed by every call below for scenes of up to n
+ * primitives and n_views cameras.  REFINE_E_INVALID on negative sizes or a
+ * NULL `bytes`. */
+refine_status refine_workspace_size(int64_t n, int32_t n_views, size_t* bytes);
+
+/*
+ * Scene features (Eq. features) and content-adaptive weights (Eq. 18, 19).
+ * Per-primitive terms in FP32, reduced in FP64 with a fixed order (results
+ * are bit-identical run to run).  Writes *d_stats (device).
+ * n = 0 writes zeros and lambda = 1/3.
+ */
+refine_status refine_stats(const refine_scene* scene, const refine_params* params,
+                           refine_stats_t* d_stats, void* d_ws, size_t ws_bytes, void* stream);
+
+/*
+ * Importance scores D_i (Eq. 7 with the Hessian weights of Eq. 20):
+ *   D_i = sum_k lambda^k G~_i^k * (1/|V|) sum_v g_i^v V_i P_i^v
+ * with the visibility V_i and projection P_i^v of the selected modes and the
+ * gate g_i^v (depth > z_near and the 3-sigma footprint of the projected
+ * covariance overlapping the image).  FP32 arithmetic, views summed in order.
+ *  d_cams    device float32 [n_views][18]: world-to-camera rotation R
+ *            (row-major), translation t (p_cam = R p + t), fx, fy, cx, cy,
+ *            W, H (pixels; Eq. 13), camera axes x right, y down, z forward
+ *  d_stats   device, the output of refine_stats for the same scene
+ *  d_scores  device float32 [n]
+ * n_views >= 1.
+ */
+refine_status refine_score(const refine_scene* scene, const float* d_cams, int32_t n_views,
+                           const refine_params* params, const refine_stats_t* d_stats,
+                           float* d_scores, void* d_ws, size_t ws_bytes, void* stream);
+
+/*
+ * Global ranking and ratio selection (Sec. 3.3): primitives are ordered by
+ * (score, index) and the first n_prune are removed, n_prune =
+ * refine_prune_count(n, ratio), or n_prune_override when it is >= 0 (then
+ * 0 <= n_prune_override <= n and ratio is ignored).  NaN scores rank above
+ * every number; -0 equals +0.
+ *  d_keep        device uint8 [n]: 1 = kept, 0 = pruned
+ *  d_n_keep      device int64 (nullable): n - n_prune
+ *  d_threshold   device uint32 (nullable): order-preserving key of the score
+ *                of the last pruned primitive (0 when nothing is pruned)
+ */
+refine_status refine_select(const float* d_scores, int64_t n, double ratio, int64_t n_prune_override,
+                            uint8_t* d_keep, int64_t* d_n_keep, uint32_t* d_threshold,
+                            void* d_ws, size_t ws_bytes, void* stream);
+
+/*
+ * Survivors of a keep mask, in their original order, all 59 planes
+ * (bit copies): out->planes[p * out->stride + j] = in->planes[p * in->stride
+ * + i_j] with i_j the j-th index whose d_keep is non-zero.  d_index_map
+ * (nullable, device int32 [out->n]) receives i_j.  out->n is the capacity:
+ * survivors beyond it are not written.  d_n_out (nullable, device int64)
+ * receives the number of survivors (which may exceed the capacity).
+ * in and out must have the same dtype and must not overlap.
+ */
+refine_status refine_compact(const refine_scene* in, const uint8_t* d_keep, const refine_scene* out,
+                             int32_t* d_index_map, int64_t* d_n_out, void* d_ws, size_t ws_bytes,
+                             void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* REFINE_H */

@@ -23,7 +23,7 @@ _lib = None
 def build(force: bool = True) -> str:
     """Compile the oracle into ``oracle/liboracle.so``."""
     global _lib
-    if not force and os.path.exists(_LIB):
+    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
         return _LIB
     tmp = _LIB + f".tmp{os.getpid()}"
     cmd = ["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off",
@@ -79,8 +79,7 @@ def load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB):
-        build()
+    build(force=False)
     lib = ctypes.CDLL(_LIB)
     P = ctypes.c_void_p
     i64 = ctypes.c_int64
@@ -103,6 +102,8 @@ def load():
     lib.oracle_select.restype = None
     lib.oracle_compact.argtypes = [P, i64, i64, P, P, i64, P]
     lib.oracle_compact.restype = i64
+    lib.oracle_num_threads.argtypes = []
+    lib.oracle_num_threads.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -197,6 +198,10 @@ def score(planes, cams, lam_, prm: Params | None = None, n=None, idx=None):
                         _ptr(lam_), _ptr(idx) if idx is not None else None, m,
                         _ptr(D), _ptr(lo), _ptr(hi), _ptr(na))
     return D, lo, hi, na
+
+
+def num_threads() -> int:
+    return int(load().oracle_num_threads())
 
 
 def n_prune(n: int, ratio: float) -> int:

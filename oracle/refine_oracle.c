@@ -30,6 +30,9 @@
  */
 #include <math.h>
 #include <stdint.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdlib.h>
 #include <string.h>
 
@@ -52,6 +55,16 @@ typedef struct {
     int32_t n_sub_views;  /* 0: all views; m > 0: views floor(j V / m), j < m */
     double amb_eps;    /* width of the FP32-reach band used to flag gate-ambiguous pairs */
 } oracle_params;
+
+/* Number of threads the OpenMP loops use (1 without OpenMP). */
+int oracle_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* ---------------------------------------------------------------- helpers */
 

@@ -1,0 +1,106 @@
+"""ctypes loader of ``librefine.so`` and mirrors of the C-ABI structures.
+
+Argument marshalling only.  Importing this module does not touch the GPU;
+loading the library fails loudly (``RuntimeError``) when it has not been
+built -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librefine.so")
+
+REFINE_OK = 0
+REFINE_E_INVALID = -1
+REFINE_E_UNSUPPORTED = -2
+REFINE_E_WORKSPACE = -3
+REFINE_E_HIP = -4
+
+REFINE_F32 = 0
+PROJ_COV, PROJ_DEPTH, PROJ_NONE = 0, 1, 2
+VIS_ALPHA, VIS_NONE = 0, 1
+
+EXPORTED = ("refine_version", "refine_status_string", "refine_params_default", "refine_prune_count",
+            "refine_workspace_size", "refine_stats", "refine_score", "refine_select", "refine_compact")
+
+
+class Scene(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("stride", ctypes.c_int64), ("dtype", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("planes", ctypes.c_void_p)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("eta", ctypes.c_double), ("z_near", ctypes.c_double), ("clamp_k", ctypes.c_double),
+                ("e_col", ctypes.c_double), ("e_opa", ctypes.c_double), ("e_lngem", ctypes.c_double),
+                ("proj_mode", ctypes.c_int32), ("vis_mode", ctypes.c_int32),
+                ("equal_lambda", ctypes.c_int32), ("n_sub_views", ctypes.c_int32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("ybar", ctypes.c_double), ("f_col", ctypes.c_double), ("f_opa", ctypes.c_double),
+                ("f_gem", ctypes.c_double), ("lam", ctypes.c_double * 3), ("n", ctypes.c_int64),
+                ("n_nonfinite", ctypes.c_int64)]
+
+
+STATS_BYTES = ctypes.sizeof(Stats)
+
+_lib = None
+
+
+class RefineError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {status_string(status)}")
+
+
+def load():
+    """Load the built library (no GPU access)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2606_09074_amd.build` "
+                           "(there is no CPU fallback)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    i64, i32, sz = ctypes.c_int64, ctypes.c_int32, ctypes.c_size_t
+    lib.refine_version.argtypes = []
+    lib.refine_version.restype = ctypes.c_char_p
+    lib.refine_status_string.argtypes = [i32]
+    lib.refine_status_string.restype = ctypes.c_char_p
+    lib.refine_params_default.argtypes = [ctypes.POINTER(Params)]
+    lib.refine_params_default.restype = None
+    lib.refine_prune_count.argtypes = [i64, ctypes.c_double]
+    lib.refine_prune_count.restype = i64
+    lib.refine_workspace_size.argtypes = [i64, i32, ctypes.POINTER(sz)]
+    lib.refine_workspace_size.restype = i32
+    lib.refine_stats.argtypes = [ctypes.POINTER(Scene), ctypes.POINTER(Params), P, P, sz, P]
+    lib.refine_stats.restype = i32
+    lib.refine_score.argtypes = [ctypes.POINTER(Scene), P, i32, ctypes.POINTER(Params), P, P, P, sz, P]
+    lib.refine_score.restype = i32
+    lib.refine_select.argtypes = [P, i64, ctypes.c_double, i64, P, P, P, P, sz, P]
+    lib.refine_select.restype = i32
+    lib.refine_compact.argtypes = [ctypes.POINTER(Scene), P, ctypes.POINTER(Scene), P, P, P, sz, P]
+    lib.refine_compact.restype = i32
+    _lib = lib
+    return lib
+
+
+def status_string(status: int) -> str:
+    try:
+        return load().refine_status_string(int(status)).decode()
+    except RuntimeError:
+        return f"status {status}"
+
+
+def check(status: int, where: str) -> None:
+    if status != REFINE_OK:
+        raise RefineError(status, where)
+
+
+def default_params() -> Params:
+    p = Params()
+    load().refine_params_default(ctypes.byref(p))
+    return p

@@ -1,0 +1,213 @@
+// C ABI of the REFINE library: argument validation (before any HIP call),
+// workspace layout and dispatch to the kernel launchers.
+#include <cmath>
+#include <cstring>
+#include <limits>
+
+#include "refine_internal.hpp"
+
+namespace refine {
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+bool finite(double x) { return std::isfinite(x); }
+
+refine_status check_scene(const refine_scene* s, bool output)
+{
+    if (!s) return REFINE_E_INVALID;
+    if (s->n < 0 || s->stride < 0 || s->stride < s->n) return REFINE_E_INVALID;
+    if (s->reserved != 0) return REFINE_E_INVALID;
+    if (s->dtype != REFINE_F32) return REFINE_E_UNSUPPORTED;
+    if (s->n > (int64_t)std::numeric_limits<int32_t>::max()) return REFINE_E_UNSUPPORTED;
+    if (s->stride > std::numeric_limits<int64_t>::max() / (kPlanes * 4)) return REFINE_E_INVALID;
+    if (s->n > 0 && !s->planes) return REFINE_E_INVALID;
+    (void)output;
+    return REFINE_OK;
+}
+
+refine_status check_params(const refine_params* p)
+{
+    if (!p) return REFINE_E_INVALID;
+    if (!finite(p->eta) || p->eta <= 0.0) return REFINE_E_INVALID;
+    if (!finite(p->z_near) || p->z_near < 0.0) return REFINE_E_INVALID;
+    if (!finite(p->clamp_k) || p->clamp_k <= 0.0) return REFINE_E_INVALID;
+    if (!finite(p->e_col) || p->e_col == 0.0) return REFINE_E_INVALID;
+    if (!finite(p->e_opa) || p->e_opa == 0.0) return REFINE_E_INVALID;
+    if (!finite(p->e_lngem) || p->e_lngem == 0.0) return REFINE_E_INVALID;
+    if (p->proj_mode < REFINE_PROJ_COV || p->proj_mode > REFINE_PROJ_NONE) return REFINE_E_INVALID;
+    if (p->vis_mode < REFINE_VIS_ALPHA || p->vis_mode > REFINE_VIS_NONE) return REFINE_E_INVALID;
+    if (p->equal_lambda != 0 && p->equal_lambda != 1) return REFINE_E_INVALID;
+    if (p->n_sub_views < 0) return REFINE_E_INVALID;
+    return REFINE_OK;
+}
+
+constexpr int32_t kMaxViews = 1 << 20;
+
+refine_status check_workspace(int64_t n, int32_t n_views, const void* ws, size_t ws_bytes, Workspace* out)
+{
+    const size_t need = workspace_layout(n, n_views, nullptr, nullptr);
+    if (ws_bytes < need || (need > 0 && !ws)) return REFINE_E_WORKSPACE;
+    workspace_layout(n, n_views, const_cast<void*>(ws), out);
+    return REFINE_OK;
+}
+
+}  // namespace
+
+size_t workspace_layout(int64_t n, int32_t n_views, void* base, Workspace* ws)
+{
+    const size_t nt = (size_t)(num_tiles(n) > 0 ? num_tiles(n) : 1);
+    size_t off = 0;
+    const size_t o_sel = off;   off += align_up(sizeof(SelectState));
+    const size_t o_hist = off;  off += align_up(sizeof(uint32_t) * kHistBins);
+    const size_t o_part = off;  off += align_up(sizeof(double) * kStatSlots * nt);
+    const size_t o_cnt = off;   off += align_up(sizeof(uint32_t) * nt);
+    const size_t o_toff = off;  off += align_up(sizeof(uint32_t) * nt);
+    // the camera table is last, so calls without cameras need a prefix only
+    const size_t o_cams = off;  off += align_up(sizeof(CamRec) * (size_t)(n_views > 0 ? n_views : 0));
+    if (base && ws) {
+        char* b = static_cast<char*>(base);
+        ws->sel = reinterpret_cast<SelectState*>(b + o_sel);
+        ws->hist = reinterpret_cast<uint32_t*>(b + o_hist);
+        ws->stat_part = reinterpret_cast<double*>(b + o_part);
+        ws->tile_cnt = reinterpret_cast<uint32_t*>(b + o_cnt);
+        ws->tile_off = reinterpret_cast<uint32_t*>(b + o_toff);
+        ws->cams = reinterpret_cast<CamRec*>(b + o_cams);
+    }
+    return off;
+}
+
+}  // namespace refine
+
+using namespace refine;
+
+extern "C" {
+
+const char* refine_version(void) { return "refine-mi355x 0.1.0 (gfx950, HIP)"; }
+
+const char* refine_status_string(int32_t status)
+{
+    switch (status) {
+    case REFINE_OK: return "REFINE_OK";
+    case REFINE_E_INVALID: return "REFINE_E_INVALID: invalid argument";
+    case REFINE_E_UNSUPPORTED: return "REFINE_E_UNSUPPORTED: unsupported by this build";
+    case REFINE_E_WORKSPACE: return "REFINE_E_WORKSPACE: workspace missing or too small";
+    case REFINE_E_HIP: return "REFINE_E_HIP: HIP launch failed";
+    default: return "unknown refine_status";
+    }
+}
+
+void refine_params_default(refine_params* p)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->eta = 0.05;
+    p->z_near = 0.2;
+    p->clamp_k = 1.3;
+    p->e_col = 8.892106e-3;
+    p->e_opa = 0.1767277;
+    p->e_lngem = -0.4890595;
+    p->proj_mode = REFINE_PROJ_COV;
+    p->vis_mode = REFINE_VIS_ALPHA;
+    p->equal_lambda = 0;
+    p->n_sub_views = 0;
+}
+
+int64_t refine_prune_count(int64_t n, double ratio)
+{
+    if (n < 0 || !std::isfinite(ratio) || !(ratio > 0.0) || !(ratio < 1.0)) return -1;
+    double k = std::floor(ratio * (double)n + 0.5);
+    if (k < 0.0) k = 0.0;
+    if (k > (double)n) k = (double)n;
+    return (int64_t)k;
+}
+
+refine_status refine_workspace_size(int64_t n, int32_t n_views, size_t* bytes)
+{
+    if (!bytes || n < 0 || n_views < 0) return REFINE_E_INVALID;
+    if (n > (int64_t)std::numeric_limits<int32_t>::max() || n_views > kMaxViews) return REFINE_E_UNSUPPORTED;
+    *bytes = workspace_layout(n, n_views, nullptr, nullptr);
+    return REFINE_OK;
+}
+
+refine_status refine_stats(const refine_scene* scene, const refine_params* params, refine_stats_t* d_stats,
+                           void* d_ws, size_t ws_bytes, void* stream)
+{
+    refine_status s = check_scene(scene, false);
+    if (s != REFINE_OK) return s;
+    if ((s = check_params(params)) != REFINE_OK) return s;
+    if (!d_stats) return REFINE_E_INVALID;
+    Workspace ws;
+    if ((s = check_workspace(scene->n, 0, d_ws, ws_bytes, &ws)) != REFINE_OK) return s;
+    const hipError_t e = launch_stats(static_cast<const float*>(scene->planes), scene->stride, scene->n, *params,
+                                      d_stats, ws, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? REFINE_OK : REFINE_E_HIP;
+}
+
+refine_status refine_score(const refine_scene* scene, const float* d_cams, int32_t n_views,
+                           const refine_params* params, const refine_stats_t* d_stats, float* d_scores,
+                           void* d_ws, size_t ws_bytes, void* stream)
+{
+    refine_status s = check_scene(scene, false);
+    if (s != REFINE_OK) return s;
+    if ((s = check_params(params)) != REFINE_OK) return s;
+    if (n_views < 1 || !d_cams || !d_stats) return REFINE_E_INVALID;
+    if (n_views > kMaxViews) return REFINE_E_UNSUPPORTED;
+    if (scene->n > 0 && !d_scores) return REFINE_E_INVALID;
+    Workspace ws;
+    if ((s = check_workspace(scene->n, n_views, d_ws, ws_bytes, &ws)) != REFINE_OK) return s;
+    const hipError_t e = launch_score(static_cast<const float*>(scene->planes), scene->stride, scene->n, d_cams,
+                                      n_views, *params, d_stats, d_scores, ws, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? REFINE_OK : REFINE_E_HIP;
+}
+
+refine_status refine_select(const float* d_scores, int64_t n, double ratio, int64_t n_prune_override,
+                            uint8_t* d_keep, int64_t* d_n_keep, uint32_t* d_threshold, void* d_ws,
+                            size_t ws_bytes, void* stream)
+{
+    if (n < 0) return REFINE_E_INVALID;
+    if (n > (int64_t)std::numeric_limits<int32_t>::max()) return REFINE_E_UNSUPPORTED;
+    if (n > 0 && (!d_scores || !d_keep)) return REFINE_E_INVALID;
+    int64_t n_prune;
+    if (n_prune_override >= 0) {
+        if (n_prune_override > n) return REFINE_E_INVALID;
+        n_prune = n_prune_override;
+    } else {
+        n_prune = refine_prune_count(n, ratio);
+        if (n_prune < 0) return REFINE_E_INVALID;
+    }
+    Workspace ws;
+    refine_status s = check_workspace(n, 0, d_ws, ws_bytes, &ws);
+    if (s != REFINE_OK) return s;
+    const hipError_t e = launch_select(d_scores, n, n_prune, d_keep, d_n_keep, d_threshold, ws,
+                                       static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? REFINE_OK : REFINE_E_HIP;
+}
+
+refine_status refine_compact(const refine_scene* in, const uint8_t* d_keep, const refine_scene* out,
+                             int32_t* d_index_map, int64_t* d_n_out, void* d_ws, size_t ws_bytes, void* stream)
+{
+    refine_status s = check_scene(in, false);
+    if (s != REFINE_OK) return s;
+    if ((s = check_scene(out, true)) != REFINE_OK) return s;
+    if (in->dtype != out->dtype) return REFINE_E_INVALID;
+    if (in->n > 0 && !d_keep) return REFINE_E_INVALID;
+    if (in->n > 0 && out->n > 0) {
+        const char* a0 = static_cast<const char*>(in->planes);
+        const char* a1 = a0 + (size_t)kPlanes * (size_t)in->stride * sizeof(float);
+        const char* b0 = static_cast<const char*>(out->planes);
+        const char* b1 = b0 + (size_t)kPlanes * (size_t)out->stride * sizeof(float);
+        if (a0 < b1 && b0 < a1) return REFINE_E_INVALID;
+    }
+    Workspace ws;
+    if ((s = check_workspace(in->n, 0, d_ws, ws_bytes, &ws)) != REFINE_OK) return s;
+    const hipError_t e = launch_compact(static_cast<const float*>(in->planes), in->stride, in->n, d_keep,
+                                        static_cast<float*>(out->planes), out->stride, out->n, d_index_map, d_n_out,
+                                        ws, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? REFINE_OK : REFINE_E_HIP;
+}
+
+}  // extern "C"

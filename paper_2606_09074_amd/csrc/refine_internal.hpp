@@ -1,0 +1,156 @@
+// Internal declarations of the REFINE HIP library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/refine.h"
+
+namespace refine {
+
+constexpr int kPlanes = 59;
+constexpr int kScorePlanes = 14;   // centre, log-scale, quaternion, opacity, SH DC
+constexpr int kCamFields = 18;
+constexpr int kBlock = 256;        // threads per block of the tile kernels (4 wave64)
+constexpr int kWaves = kBlock / 64;
+constexpr int kItems = 16;         // elements per thread of the tile kernels
+constexpr int kTile = kBlock * kItems;
+constexpr int kCamRec = 32;        // floats per prepared camera record
+constexpr int kHistBits = 11;
+constexpr int kHistBins = 1 << kHistBits;
+constexpr int kStatSlots = 8;      // doubles per stats partial
+
+// Prepared camera record (fp32, 128 bytes), built by camera_prep.
+struct CamRec {
+    float r[9];        // world-to-camera rotation, rows
+    float t[3];
+    float fr0[3];      // fx * row 0
+    float fr1[3];      // fy * row 1
+    float fx, fy;
+    float ox, oy;      // cx - W/2, cy - H/2
+    float hw, hh;      // W/2, H/2
+    float lx, ly;      // clamp_k * W/2, clamp_k * H/2 (pixels)
+    float kv;          // 1 / (fx^2 + fy^2)
+    float pad[5];
+};
+static_assert(sizeof(CamRec) == kCamRec * sizeof(float), "camera record size");
+
+// Device-resident state of one selection (lives in the workspace).
+struct SelectState {
+    int64_t n;
+    int64_t n_prune;
+    int64_t rank;       // 0-based rank still to be located inside the current prefix bucket
+    int64_t k_eq;       // pruned primitives whose key equals the threshold
+    int64_t n_keep;
+    uint32_t prefix;    // resolved high bits of the threshold key
+    uint32_t mask;
+    uint32_t threshold;
+    uint32_t pad[7];
+};
+
+struct Workspace {
+    SelectState* sel;
+    uint32_t* hist;          // [kHistBins]
+    double* stat_part;       // [ntiles][kStatSlots]
+    uint32_t* tile_cnt;      // [ntiles]
+    uint32_t* tile_off;      // [ntiles]
+    CamRec* cams;            // [n_views]
+};
+
+inline int64_t num_tiles(int64_t n) { return (n + kTile - 1) / kTile; }
+
+// Bytes of a workspace for (n, n_views); fills *ws when base != nullptr.
+size_t workspace_layout(int64_t n, int32_t n_views, void* base, Workspace* ws);
+
+// Launchers (validated arguments; return the hipGetLastError of the launch).
+hipError_t launch_stats(const float* planes, int64_t stride, int64_t n, const refine_params& prm,
+                        refine_stats_t* d_stats, const Workspace& ws, hipStream_t stream);
+hipError_t launch_score(const float* planes, int64_t stride, int64_t n, const float* d_cams,
+                        int32_t n_views, const refine_params& prm, const refine_stats_t* d_stats,
+                        float* d_scores, const Workspace& ws, hipStream_t stream);
+hipError_t launch_select(const float* d_scores, int64_t n, int64_t n_prune, uint8_t* d_keep,
+                         int64_t* d_n_keep, uint32_t* d_threshold, const Workspace& ws,
+                         hipStream_t stream);
+hipError_t launch_compact(const float* in, int64_t in_stride, int64_t n, const uint8_t* d_keep,
+                          float* out, int64_t out_stride, int64_t capacity, int32_t* d_index_map,
+                          int64_t* d_n_out, const Workspace& ws, hipStream_t stream);
+
+// ------------------------------------------------------------ device helpers
+
+// Sum over a wave64 by xor butterflies: every lane ends with the same value,
+// and the association order depends only on lane positions (deterministic).
+__device__ inline double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ inline uint32_t wave_sum_u32(uint32_t v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Number of set bits of a wave ballot below this lane.
+__device__ inline uint32_t lanes_below(uint64_t ballot)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(ballot >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)ballot, 0u));
+}
+
+// Order-preserving unsigned key of a float: a < b  <=>  key(a) < key(b);
+// -0 maps to the key of +0 and every NaN to the largest key.
+__device__ inline uint32_t float_key(float f)
+{
+    if (f != f) return 0xFFFFFFFFu;
+    uint32_t u = __float_as_uint(f);
+    if (u == 0x80000000u) u = 0u;
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+}  // namespace refine
+
+namespace refine {
+
+constexpr int kScanThreads = 1024;
+
+// Exclusive prefix sum of cnt[0..m) into off[0..m) by one block of
+// kScanThreads threads (each thread scans a contiguous chunk); returns the
+// total in every thread.  Integer only, so the result is exact.
+__device__ inline uint32_t block_exclusive_scan(const uint32_t* __restrict__ cnt, uint32_t* __restrict__ off,
+                                                int m)
+{
+    __shared__ uint32_t wave_tot[kScanThreads / 64];
+    const int chunk = (m + kScanThreads - 1) / kScanThreads;
+    const int lo = threadIdx.x * chunk;
+    const int hi = min(lo + chunk, m);
+    uint32_t local = 0;
+    for (int j = lo; j < hi; ++j) local += cnt[j];
+    // inclusive scan of `local` across the wave
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t incl = local;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += y;
+    }
+    if (lane == 63) wave_tot[wave] = incl;
+    __syncthreads();
+    uint32_t before = 0, total = 0;
+    for (int w = 0; w < kScanThreads / 64; ++w) {
+        if (w < wave) before += wave_tot[w];
+        total += wave_tot[w];
+    }
+    uint32_t run = before + incl - local;
+    for (int j = lo; j < hi; ++j) {
+        off[j] = run;
+        run += cnt[j];
+    }
+    return total;
+}
+
+}  // namespace refine

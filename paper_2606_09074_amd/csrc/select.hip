@@ -1,0 +1,215 @@
+// Global ranking and ratio selection (paper Sec. 3.3) on gfx950.
+//
+// Scores become order-preserving 32-bit keys.  The key of the n_prune-th
+// smallest primitive (the threshold T) is found by three most-significant-
+// digit-first radix passes (11, 11, 10 bits): each pass histograms the keys
+// that share the already-resolved prefix into per-wave LDS histograms,
+// merges them into one global histogram with integer atomics (exact and
+// order-independent), and a single-block pass picks the bucket that holds
+// the target rank.  Ties at T are broken by index: the pruned primitives are
+// every key < T plus the k_eq lowest-index keys == T, located with wave
+// ballots and an exact prefix over tiles.  Integer arithmetic throughout, so
+// the mask equals a stable sort by (score, index).
+#include "refine_internal.hpp"
+
+namespace refine {
+
+namespace {
+
+constexpr int kPassShift[3] = {21, 10, 0};
+constexpr int kPassBits[3] = {11, 11, 10};
+
+__global__ void select_init(SelectState* __restrict__ st, uint32_t* __restrict__ hist, int64_t n, int64_t n_prune)
+{
+    for (int b = threadIdx.x; b < kHistBins; b += blockDim.x) hist[b] = 0u;
+    if (threadIdx.x == 0) {
+        SelectState s = {};
+        s.n = n;
+        s.n_prune = n_prune;
+        s.rank = n_prune - 1;
+        s.k_eq = 0;
+        s.n_keep = n - n_prune;
+        s.prefix = 0u;
+        s.mask = 0u;
+        s.threshold = 0u;
+        *st = s;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void select_hist(const float* __restrict__ scores, int n,
+                                                        const SelectState* __restrict__ st, int shift, int bits,
+                                                        uint32_t* __restrict__ hist)
+{
+    __shared__ uint32_t h[kWaves][kHistBins];
+    const int wave = threadIdx.x >> 6;
+    for (int b = threadIdx.x; b < kWaves * kHistBins; b += kBlock) (&h[0][0])[b] = 0u;
+    __syncthreads();
+    const uint32_t prefix = st->prefix, mask = st->mask;
+    const uint32_t dmask = (1u << bits) - 1u;
+    const int base = blockIdx.x * kTile;
+#pragma unroll 4
+    for (int k = 0; k < kItems; ++k) {
+        const int i = base + k * kBlock + (int)threadIdx.x;
+        if (i < n) {
+            const uint32_t key = float_key(scores[i]);
+            if ((key & mask) == prefix) atomicAdd(&h[wave][(key >> shift) & dmask], 1u);
+        }
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b <= (int)dmask; b += kBlock) {
+        uint32_t c = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) c += h[w][b];
+        if (c) atomicAdd(&hist[b], c);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void select_find(SelectState* __restrict__ st, uint32_t* __restrict__ hist,
+                                                        int shift, int bits, int last)
+{
+    constexpr int kPer = kHistBins / kBlock;   // 8 bins per thread
+    __shared__ uint32_t wave_tot[kWaves];
+    // read before the barrier: the thread that finds the bucket rewrites the state after it
+    const int64_t rank = st->rank;
+    const int nb = 1 << bits;
+    uint32_t h[kPer];
+    uint32_t local = 0;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const int b = threadIdx.x * kPer + j;
+        h[j] = b < nb ? hist[b] : 0u;
+        local += h[j];
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t incl = local;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += y;
+    }
+    if (lane == 63) wave_tot[wave] = incl;
+    __syncthreads();
+    uint32_t before = 0;
+    for (int w = 0; w < wave; ++w) before += wave_tot[w];
+    int64_t run = (int64_t)before + incl - local;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const int b = threadIdx.x * kPer + j;
+        if (rank >= run && rank < run + (int64_t)h[j]) {
+            SelectState s = *st;
+            s.prefix |= (uint32_t)b << shift;
+            s.mask |= ((1u << bits) - 1u) << shift;
+            s.rank = rank - run;
+            if (last) {
+                s.threshold = s.prefix;
+                s.k_eq = s.rank + 1;
+            }
+            *st = s;
+        }
+        run += h[j];
+    }
+    // every thread has read its bins before the barrier above: clear for the next pass
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) hist[threadIdx.x * kPer + j] = 0u;
+}
+
+__global__ __launch_bounds__(kBlock) void select_count(const float* __restrict__ scores, int n,
+                                                         const SelectState* __restrict__ st,
+                                                         uint32_t* __restrict__ tile_cnt)
+{
+    const uint32_t T = st->threshold;
+    const int base = blockIdx.x * kTile;
+    uint32_t c = 0;
+#pragma unroll 4
+    for (int k = 0; k < kItems; ++k) {
+        const int i = base + k * kBlock + (int)threadIdx.x;
+        if (i < n && float_key(scores[i]) == T) ++c;
+    }
+    c = wave_sum_u32(c);
+    __shared__ uint32_t red[kWaves];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int w = 0; w < kWaves; ++w) t += red[w];
+        tile_cnt[blockIdx.x] = t;
+    }
+}
+
+__global__ __launch_bounds__(kScanThreads) void select_scan(const uint32_t* __restrict__ tile_cnt,
+                                                              uint32_t* __restrict__ tile_off, int ntiles,
+                                                              const SelectState* __restrict__ st,
+                                                              int64_t* __restrict__ d_n_keep,
+                                                              uint32_t* __restrict__ d_threshold)
+{
+    block_exclusive_scan(tile_cnt, tile_off, ntiles);
+    if (threadIdx.x == 0) {
+        if (d_n_keep) *d_n_keep = st->n_keep;
+        if (d_threshold) *d_threshold = st->threshold;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void select_mask(const float* __restrict__ scores, int n,
+                                                        const SelectState* __restrict__ st,
+                                                        const uint32_t* __restrict__ tile_off,
+                                                        uint8_t* __restrict__ keep)
+{
+    __shared__ uint32_t cnt[kItems][kWaves];
+    const uint32_t T = st->threshold;
+    const int64_t k_eq = st->k_eq;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int base = blockIdx.x * kTile;
+    uint32_t key[kItems];
+    uint64_t eqb[kItems];
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        const int i = base + k * kBlock + (int)threadIdx.x;
+        key[k] = i < n ? float_key(scores[i]) : 0u;
+        eqb[k] = __ballot(i < n && key[k] == T);
+        if (lane == 0) cnt[k][wave] = (uint32_t)__popcll(eqb[k]);
+    }
+    __syncthreads();
+    int64_t row = (int64_t)tile_off[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        const int i = base + k * kBlock + (int)threadIdx.x;
+        uint32_t before = 0, tot = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) {
+            if (w < wave) before += cnt[k][w];
+            tot += cnt[k][w];
+        }
+        const int64_t eq_rank = row + before + lanes_below(eqb[k]);
+        const bool pruned = key[k] < T || (key[k] == T && eq_rank < k_eq);
+        if (i < n) keep[i] = pruned ? 0 : 1;
+        row += tot;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_select(const float* d_scores, int64_t n, int64_t n_prune, uint8_t* d_keep, int64_t* d_n_keep,
+                         uint32_t* d_threshold, const Workspace& ws, hipStream_t stream)
+{
+    const int ntiles = (int)num_tiles(n);
+    hipLaunchKernelGGL(select_init, dim3(1), dim3(kBlock), 0, stream, ws.sel, ws.hist, n, n_prune);
+    if (n_prune > 0) {
+        for (int p = 0; p < 3; ++p) {
+            hipLaunchKernelGGL(select_hist, dim3(ntiles), dim3(kBlock), 0, stream, d_scores, (int)n, ws.sel,
+                               kPassShift[p], kPassBits[p], ws.hist);
+            hipLaunchKernelGGL(select_find, dim3(1), dim3(kBlock), 0, stream, ws.sel, ws.hist, kPassShift[p],
+                               kPassBits[p], p == 2 ? 1 : 0);
+        }
+    }
+    if (ntiles > 0)
+        hipLaunchKernelGGL(select_count, dim3(ntiles), dim3(kBlock), 0, stream, d_scores, (int)n, ws.sel,
+                           ws.tile_cnt);
+    hipLaunchKernelGGL(select_scan, dim3(1), dim3(kScanThreads), 0, stream, ws.tile_cnt, ws.tile_off, ntiles, ws.sel,
+                       d_n_keep, d_threshold);
+    if (ntiles > 0)
+        hipLaunchKernelGGL(select_mask, dim3(ntiles), dim3(kBlock), 0, stream, d_scores, (int)n, ws.sel,
+                           ws.tile_off, d_keep);
+    return hipGetLastError();
+}
+
+}  // namespace refine

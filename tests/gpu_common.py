@@ -1,0 +1,137 @@
+"""Helpers of the GPU parity tests: run the library through its C ABI on
+seeded inputs, run the oracle on the same inputs, compare."""
+from __future__ import annotations
+
+import functools
+import sys
+
+import numpy as np
+
+from tests.helpers import (ABS_TOL, CLAMP_K, E_COL, E_LNGEM, E_OPA, ETA, REL_TOL, Z_NEAR, within_interval)
+
+
+def log(msg: str) -> None:
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_params(**kw):
+    from paper_2606_09074_amd import _lib
+    p = _lib.Params(ETA, Z_NEAR, CLAMP_K, E_COL, E_OPA, E_LNGEM, 0, 0, 0, 0)
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def oracle_params(**kw):
+    import oracle
+    return oracle.Params(eta=ETA, z_near=Z_NEAR, clamp_k=CLAMP_K, e_col=E_COL, e_opa=E_OPA, e_lngem=E_LNGEM,
+                         **kw)
+
+
+def run_gpu(planes: np.ndarray, cams: np.ndarray, n: int | None = None, ratio: float | None = None,
+            n_prune: int = -1, params=None, repeat: int = 1) -> dict:
+    """Stats, score and (optionally) select + compact on cuda:0."""
+    import torch
+
+    from paper_2606_09074_amd import _lib, api
+    n = planes.shape[1] if n is None else n
+    dev = torch.device("cuda:0")
+    pl = torch.from_numpy(np.ascontiguousarray(planes)).to(dev)
+    cm = torch.from_numpy(np.ascontiguousarray(cams)).to(dev)
+    ws = api.workspace(n, cams.shape[0], dev)
+    st = torch.empty(_lib.STATS_BYTES, dtype=torch.uint8, device=dev)
+    scores = torch.full((max(n, 1),), float("nan"), dtype=torch.float32, device=dev)
+    params = params or gpu_params()
+    res = {}
+    outs = []
+    for _ in range(repeat):
+        api.refine_stats(pl, st, ws, params, n=n)
+        api.refine_score(pl, cm, st, scores, ws, params, n=n)
+        outs.append(scores[:n].cpu().numpy().copy())
+    torch.cuda.synchronize()
+    res["stats"] = api.stats_from_tensor(st)
+    res["scores"] = outs[0]
+    res["runs"] = outs
+    if ratio is not None or n_prune >= 0:
+        keep = torch.full((max(n, 1),), 7, dtype=torch.uint8, device=dev)
+        nk = torch.full((1,), -1, dtype=torch.int64, device=dev)
+        thr = torch.zeros(1, dtype=torch.int32, device=dev)
+        api.refine_select(scores, keep, ws, ratio=ratio if ratio is not None else 0.5, n_prune=n_prune,
+                          n_keep_out=nk, threshold_out=thr, n=n)
+        k = int(nk.item())
+        cap = max(k, 0)
+        out = torch.full((59, max(cap, 1) + 3), float("nan"), dtype=torch.float32, device=dev)
+        idx = torch.full((max(cap, 1) + 3,), -7, dtype=torch.int32, device=dev)
+        nout = torch.full((1,), -1, dtype=torch.int64, device=dev)
+        api.refine_compact(pl, keep, out, ws, index_map_out=idx, n_out=nout, n=n, capacity=cap)
+        torch.cuda.synchronize()
+        res["keep"] = keep[:n].cpu().numpy()
+        res["n_keep"] = k
+        res["threshold"] = int(thr.item()) & 0xFFFFFFFF
+        res["out"] = out.cpu().numpy()
+        res["index_map"] = idx.cpu().numpy()
+        res["n_out"] = int(nout.item())
+        res["capacity"] = cap
+    return res
+
+
+def float_keys(x: np.ndarray) -> np.ndarray:
+    """Order-preserving uint32 keys of float32 values (numpy, for checks)."""
+    x = np.asarray(x, dtype=np.float32).copy()
+    x[x == 0] = 0.0                      # -0 -> +0
+    u = x.view(np.uint32).astype(np.uint64)
+    key = np.where(u & 0x80000000, (~u) & 0xFFFFFFFF, u | 0x80000000)
+    key[np.isnan(x)] = 0xFFFFFFFF
+    return key.astype(np.uint64)
+
+
+def expected_keep_from_scores(scores: np.ndarray, n_prune: int) -> np.ndarray:
+    n = scores.size
+    order = np.lexsort((np.arange(n), float_keys(scores)))
+    keep = np.ones(n, dtype=np.uint8)
+    keep[order[:n_prune]] = 0
+    return keep
+
+
+def check_scores(gpu: np.ndarray, D: np.ndarray, lo: np.ndarray, hi: np.ndarray, what: str) -> dict:
+    ok = within_interval(gpu, lo, hi)
+    bad = np.nonzero(~ok)[0]
+    rel = np.abs(gpu.astype(np.float64) - D) / np.maximum(np.abs(D), ABS_TOL / REL_TOL)
+    amb = lo != hi
+    summary = {"n": gpu.size, "max_rel_unambiguous": float(rel[~amb].max()) if (~amb).any() else 0.0,
+               "n_interval": int(amb.sum()), "n_fail": int(bad.size)}
+    log(f"[{what}] {summary}")
+    if bad.size:
+        j = bad[:10]
+        raise AssertionError(f"{what}: {bad.size} scores outside tolerance; idx {j}, gpu {gpu[j]}, "
+                             f"oracle {D[j]}, lo {lo[j]}, hi {hi[j]}")
+    return summary
+
+
+def check_mask_vs_oracle(keep_gpu, D, lo, hi, n_prune: int, what: str) -> int:
+    import oracle
+    n = D.size
+    keep_o, order = oracle.select(D, n_prune)
+    assert int(keep_gpu.sum()) == int(keep_o.sum()) == n - n_prune
+    if n_prune == 0 or n_prune == n:
+        np.testing.assert_array_equal(keep_gpu, keep_o)
+        return 0
+    tau_lo = D[order[n_prune - 1]]
+    tau_hi = D[order[n_prune]]
+    tol = lambda x: np.maximum(REL_TOL * np.abs(x), ABS_TOL)
+    border = (lo - tol(lo) <= tau_hi + tol(tau_hi)) & (hi + tol(hi) >= tau_lo - tol(tau_lo))
+    diff = keep_gpu.astype(bool) != keep_o.astype(bool)
+    bad = diff & ~border
+    log(f"[{what}] mask differs on {int(diff.sum())} primitives, {int(border.sum())} borderline")
+    assert not bad.any(), f"{what}: {int(bad.sum())} non-borderline mask differences, e.g. {np.nonzero(bad)[0][:10]}"
+    return int(diff.sum())
+
+
+@functools.lru_cache(maxsize=4)
+def workload(name: str, n: int | None = None):
+    from paper_2606_09074_amd import synth
+    spec = synth.SPECS[name]
+    if n is not None:
+        spec = spec.with_n(n)
+    return synth.make_planes(spec), synth.make_cameras(spec), spec

@@ -1,0 +1,162 @@
+"""C-ABI boundary checks that need no GPU: the library loads, exports every
+function the header declares, and rejects invalid arguments on the host
+before any HIP call (these calls never reach a kernel launch)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from tests.conftest import ROOT
+
+HEADER = os.path.join(ROOT, "include", "refine.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2606_09074_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2606_09074_amd import build
+        build.build()
+    return _lib.load()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^[A-Za-z_][\w\s\*]*?\b(refine_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_every_declared_function_is_exported(lib):
+    from paper_2606_09074_amd import _lib
+    names = declared_functions()
+    assert set(names) == set(_lib.EXPORTED)
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = set(re.findall(r"\sT\s(refine_\w+)$", out, flags=re.M))
+    for name in names:
+        assert name in exported, name
+        assert getattr(lib, name) is not None
+
+
+def test_struct_sizes_match_header():
+    from paper_2606_09074_amd import _lib
+    assert ctypes.sizeof(_lib.Scene) == 32
+    assert ctypes.sizeof(_lib.Params) == 64
+    assert ctypes.sizeof(_lib.Stats) == 72
+
+
+def test_version_status_defaults(lib):
+    from paper_2606_09074_amd import _lib
+    assert b"gfx950" in lib.refine_version()
+    assert lib.refine_status_string(_lib.REFINE_E_WORKSPACE).startswith(b"REFINE_E_WORKSPACE")
+    p = _lib.default_params()
+    from tests.helpers import CLAMP_K, E_COL, E_LNGEM, E_OPA, ETA, Z_NEAR
+    assert (p.eta, p.z_near, p.clamp_k, p.e_col, p.e_opa, p.e_lngem) == (ETA, Z_NEAR, CLAMP_K, E_COL, E_OPA,
+                                                                          E_LNGEM)
+    assert (p.proj_mode, p.vis_mode, p.equal_lambda, p.n_sub_views) == (0, 0, 0, 0)
+
+
+def test_prune_count(lib):
+    assert lib.refine_prune_count(5, 0.5) == 3
+    assert lib.refine_prune_count(3_000_000, 0.9) == 2_700_000
+    assert lib.refine_prune_count(6_000_000, 0.66) == 3_960_000
+    for bad in (0.0, 1.0, -0.1, float("nan"), float("inf")):
+        assert lib.refine_prune_count(10, bad) == -1
+    assert lib.refine_prune_count(-1, 0.5) == -1
+
+
+def test_workspace_size(lib):
+    from paper_2606_09074_amd import _lib
+    sz = ctypes.c_size_t()
+    assert lib.refine_workspace_size(3_000_000, 200, ctypes.byref(sz)) == 0
+    big = sz.value
+    assert lib.refine_workspace_size(1000, 16, ctypes.byref(sz)) == 0
+    assert 0 < sz.value < big
+    assert lib.refine_workspace_size(-1, 16, ctypes.byref(sz)) == _lib.REFINE_E_INVALID
+    assert lib.refine_workspace_size(10, -1, ctypes.byref(sz)) == _lib.REFINE_E_INVALID
+    assert lib.refine_workspace_size(1 << 31, 16, ctypes.byref(sz)) == _lib.REFINE_E_UNSUPPORTED
+    assert lib.refine_workspace_size(10, 16, None) == _lib.REFINE_E_INVALID
+
+
+FAKE = 0x10000   # never dereferenced: every call below fails validation first
+
+
+def _scene(n=100, stride=None, dtype=0, reserved=0, planes=FAKE):
+    from paper_2606_09074_amd import _lib
+    return _lib.Scene(n, n if stride is None else stride, dtype, reserved, ctypes.c_void_p(planes))
+
+
+def test_stats_validation(lib):
+    from paper_2606_09074_amd import _lib
+    p = _lib.default_params()
+    ws_ok = 1 << 30
+    E = _lib.REFINE_E_INVALID
+    call = lambda sc, prm=p, out=FAKE, ws=FAKE, wsb=ws_ok: lib.refine_stats(
+        ctypes.byref(sc) if sc is not None else None, ctypes.byref(prm) if prm is not None else None,
+        out, ws, wsb, None)
+    assert call(None) == E
+    assert call(_scene(n=-1)) == E
+    assert call(_scene(n=10, stride=5)) == E
+    assert call(_scene(reserved=1)) == E
+    assert call(_scene(planes=0)) == E
+    assert call(_scene(dtype=7)) == _lib.REFINE_E_UNSUPPORTED
+    assert call(_scene(n=1 << 31)) == _lib.REFINE_E_UNSUPPORTED
+    assert call(_scene(), prm=None) == E
+    assert call(_scene(), out=None) == E
+    assert call(_scene(), ws=None) == _lib.REFINE_E_WORKSPACE
+    assert call(_scene(), wsb=16) == _lib.REFINE_E_WORKSPACE
+    for field, bad in (("eta", 0.0), ("eta", float("nan")), ("z_near", -1.0), ("clamp_k", 0.0),
+                       ("e_col", 0.0), ("e_lngem", float("inf")), ("proj_mode", 3), ("vis_mode", -1),
+                       ("equal_lambda", 2), ("n_sub_views", -5)):
+        q = _lib.default_params()
+        setattr(q, field, bad)
+        assert call(_scene(), prm=q) == E, field
+
+
+def test_score_validation(lib):
+    from paper_2606_09074_amd import _lib
+    p = _lib.default_params()
+    E = _lib.REFINE_E_INVALID
+    sc = _scene()
+
+    def call(nv=16, cams=FAKE, stats=FAKE, scores=FAKE, ws=FAKE, wsb=1 << 30, scene=sc):
+        return lib.refine_score(ctypes.byref(scene), cams, nv, ctypes.byref(p), stats, scores, ws, wsb, None)
+    assert call(nv=0) == E
+    assert call(nv=-3) == E
+    assert call(cams=None) == E
+    assert call(stats=None) == E
+    assert call(scores=None) == E
+    assert call(nv=(1 << 20) + 1) == _lib.REFINE_E_UNSUPPORTED
+    assert call(wsb=100) == _lib.REFINE_E_WORKSPACE
+
+
+def test_select_validation(lib):
+    from paper_2606_09074_amd import _lib
+    E = _lib.REFINE_E_INVALID
+
+    def call(n=100, ratio=0.5, ov=-1, scores=FAKE, keep=FAKE, wsb=1 << 30, ws=FAKE):
+        return lib.refine_select(scores, n, ratio, ov, keep, None, None, ws, wsb, None)
+    for r in (0.0, 1.0, 1.5, -0.2, float("nan")):
+        assert call(ratio=r) == E
+    assert call(ov=101) == E
+    assert call(n=-1) == E
+    assert call(scores=None) == E
+    assert call(keep=None) == E
+    assert call(wsb=10) == _lib.REFINE_E_WORKSPACE
+
+
+def test_compact_validation(lib):
+    from paper_2606_09074_amd import _lib
+    E = _lib.REFINE_E_INVALID
+    sin = _scene(n=100)
+
+    def call(src=sin, dst=None, keep=FAKE, ws=FAKE, wsb=1 << 30):
+        dst = dst if dst is not None else _scene(n=50, planes=0x4000000)
+        return lib.refine_compact(ctypes.byref(src), keep, ctypes.byref(dst), None, None, ws, wsb, None)
+    assert call(keep=None) == E
+    assert call(dst=_scene(n=50, planes=FAKE + 64)) == E                 # overlapping buffers
+    assert call(dst=_scene(n=50, dtype=7, planes=0x4000000)) == _lib.REFINE_E_UNSUPPORTED
+    assert call(dst=_scene(n=50, stride=10, planes=0x4000000)) == E
+    assert call(wsb=8) == _lib.REFINE_E_WORKSPACE

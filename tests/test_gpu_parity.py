@@ -1,0 +1,274 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle on the
+same seeded inputs.
+
+Scores: |D_gpu - D_ref| <= max(1e-4 |D_ref|, 1e-7), widened to the oracle's
+[D_lo, D_hi] where a gate decision lies within FP32 reach.  Masks: equal to a
+stable sort of the GPU's own scores (bit-exact) and to the oracle's mask
+except for primitives within tolerance of the threshold.  Compaction:
+bit-exact given the mask.  Scene statistics: relative 1e-6 (per-primitive
+FP32 terms, FP64 sums).
+"""
+import numpy as np
+import pytest
+
+from tests.gpu_common import (check_mask_vs_oracle, check_scores, expected_keep_from_scores, gpu_params, log,
+                              oracle_params, run_gpu, workload)
+from tests.helpers import camera, planes_from_prims, raw_prim
+
+pytestmark = pytest.mark.gpu
+
+STATS_RTOL = 1e-6
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2606_09074_amd import _lib
+    _lib.load()
+
+
+def oracle_all(planes, cams, n=None, **kw):
+    import oracle
+    prm = oracle_params(**kw)
+    F = oracle.stats(planes, n=n, eta=prm.eta)
+    lam = oracle.lam(F, prm)
+    D, lo, hi, na = oracle.score(planes, cams, lam, prm, n=n)
+    return F, lam, D, lo, hi
+
+
+def check_stats(gs, F, lam, what):
+    for k in ("ybar", "f_col", "f_opa", "f_gem"):
+        assert abs(gs[k] - F[k]) <= STATS_RTOL * abs(F[k]) + 1e-15, (what, k, gs[k], F[k])
+    np.testing.assert_allclose(gs["lambda"], lam, rtol=STATS_RTOL, atol=1e-12)
+
+
+def test_small_workload_full_pipeline():
+    planes, cams, spec = workload("small")
+    log(f"small: n={spec.n} V={cams.shape[0]}")
+    F, lam, D, lo, hi = oracle_all(planes, cams)
+    import oracle
+    n_prune = oracle.n_prune(spec.n, 0.5)
+    r = run_gpu(planes, cams, ratio=0.5)
+    check_stats(r["stats"], F, lam, "small")
+    assert r["stats"]["n"] == spec.n and r["stats"]["n_nonfinite"] == 0
+    check_scores(r["scores"], D, lo, hi, "small scores")
+    np.testing.assert_array_equal(r["keep"], expected_keep_from_scores(r["scores"], n_prune))
+    check_mask_vs_oracle(r["keep"], D, lo, hi, n_prune, "small mask")
+    _check_compact(planes, spec.n, r)
+
+
+def _check_compact(planes, n, r):
+    keep = r["keep"].astype(bool)
+    k = int(keep.sum())
+    assert r["n_keep"] == k and r["n_out"] == k
+    ref = planes[:, :n][:, keep]
+    np.testing.assert_array_equal(r["out"][:, :k].view(np.uint32), ref.view(np.uint32))
+    np.testing.assert_array_equal(r["index_map"][:k], np.nonzero(keep)[0].astype(np.int32))
+    # nothing beyond the capacity was written
+    assert np.all(np.isnan(r["out"][:, k:])) and np.all(r["index_map"][k:] == -7)
+
+
+@pytest.mark.parametrize("n", [1, 63, 64, 65, 255, 256, 257, 4095, 4096, 4097, 9000])
+def test_ragged_sizes(n):
+    planes, cams, _ = workload("small")
+    sub = np.ascontiguousarray(planes[:, :n])
+    F, lam, D, lo, hi = oracle_all(sub, cams)
+    r = run_gpu(sub, cams, ratio=0.5)
+    check_stats(r["stats"], F, lam, f"n={n}")
+    check_scores(r["scores"], D, lo, hi, f"n={n}")
+    import oracle
+    n_prune = oracle.n_prune(n, 0.5)
+    np.testing.assert_array_equal(r["keep"], expected_keep_from_scores(r["scores"], n_prune))
+    _check_compact(sub, n, r)
+
+
+def test_padded_stride():
+    from paper_2606_09074_amd import synth
+    spec = synth.SMALL.with_n(5000)
+    planes = synth.make_planes(spec, stride=5000 + 37)
+    planes[:, 5000:] = np.nan                       # padding must never be read
+    cams = synth.make_cameras(spec)
+    F, lam, D, lo, hi = oracle_all(planes, cams, n=5000)
+    r = run_gpu(planes, cams, n=5000, ratio=0.3)
+    check_stats(r["stats"], F, lam, "padded")
+    assert r["stats"]["n_nonfinite"] == 0
+    check_scores(r["scores"], D, lo, hi, "padded")
+    _check_compact(planes, 5000, r)
+
+
+def test_empty_scene():
+    planes = np.zeros((59, 4), dtype=np.float32)
+    cams = workload("small")[1]
+    r = run_gpu(planes, cams, n=0, ratio=0.5)
+    assert r["stats"]["n"] == 0 and r["stats"]["lambda"] == [1 / 3] * 3
+    assert r["n_keep"] == 0 and r["n_out"] == 0
+
+
+@pytest.mark.parametrize("mode", [dict(proj_mode=1), dict(proj_mode=2), dict(vis_mode=1), dict(equal_lambda=1),
+                                  dict(n_sub_views=5), dict(proj_mode=1, vis_mode=1, n_sub_views=7)])
+def test_method_switches(mode):
+    planes, cams, _ = workload("small")
+    sub = np.ascontiguousarray(planes[:, :20000])
+    F, lam, D, lo, hi = oracle_all(sub, cams, **mode)
+    r = run_gpu(sub, cams, params=gpu_params(**mode))
+    check_stats(r["stats"], F, lam, str(mode))
+    check_scores(r["scores"], D, lo, hi, str(mode))
+
+
+def test_single_and_many_views():
+    planes, cams, spec = workload("small")
+    sub = np.ascontiguousarray(planes[:, :8000])
+    for rig in (cams[:1], np.concatenate([cams] * 40)):   # 1 and 640 views
+        F, lam, D, lo, hi = oracle_all(sub, rig)
+        r = run_gpu(sub, rig)
+        check_scores(r["scores"], D, lo, hi, f"V={rig.shape[0]}")
+
+
+def test_hand_built_degenerate_primitives():
+    """Identity-less quaternion, isotropic and needle-like scales, primitives
+    on the optical axis, at the near plane, behind and far outside."""
+    prims = [raw_prim(mu=(0, 0, 3.0), quat=(0, 0, 0, 0)),
+             raw_prim(mu=(0, 0, 3.0), log_scale=(-1.0, -9.0, -9.0), quat=(0.3, 0.5, -0.2, 0.7)),
+             raw_prim(mu=(0.01, -0.02, 0.2), log_scale=(-3, -3, -3)),
+             raw_prim(mu=(0, 0, -5.0)),
+             raw_prim(mu=(500.0, 0, 3.0)),
+             raw_prim(mu=(0.2, 0.1, 1.5), log_scale=(-8, -2, -8), logit=8.0, dc=(3, -3, 1)),
+             raw_prim(mu=(0, 0, 40.0), logit=-9.0)]
+    planes = planes_from_prims(prims)
+    cams = np.stack([camera(), camera(t=(0.1, 0.0, 0.5), fx=500.0, fy=450.0)])
+    F, lam, D, lo, hi = oracle_all(planes, cams)
+    r = run_gpu(planes, cams, n_prune=3)
+    check_stats(r["stats"], F, lam, "hand-built")
+    check_scores(r["scores"], D, lo, hi, "hand-built")
+    assert r["scores"][3] == 0.0 and r["scores"][4] == 0.0
+    np.testing.assert_array_equal(r["keep"], expected_keep_from_scores(r["scores"], 3))
+
+
+def test_nonfinite_inputs_are_counted():
+    planes, cams, _ = workload("small")
+    sub = np.ascontiguousarray(planes[:, :3000])
+    sub[0, 5] = np.nan
+    sub[4, 17] = np.inf
+    sub[9, 17] = -np.inf
+    sub[13, 2999] = np.nan
+    sub[30, 100] = np.nan                 # higher SH: not read by the scoring
+    r = run_gpu(sub, cams)
+    import oracle
+    assert r["stats"]["n_nonfinite"] == oracle.nonfinite(sub) == 3
+
+
+def test_deterministic_and_permutation_consistent():
+    planes, cams, _ = workload("small")
+    r = run_gpu(planes, cams, repeat=3)
+    for other in r["runs"][1:]:
+        np.testing.assert_array_equal(other.view(np.uint32), r["runs"][0].view(np.uint32))
+    perm = np.random.default_rng(9).permutation(planes.shape[1])
+    rp = run_gpu(np.ascontiguousarray(planes[:, perm]), cams)
+    np.testing.assert_array_equal(rp["scores"].view(np.uint32), r["scores"][perm].view(np.uint32))
+
+
+@pytest.mark.parametrize("n_prune", [0, 1, 2, 4999, 5000])
+def test_select_edges_and_ties(n_prune):
+    import torch
+
+    from paper_2606_09074_amd import api
+    n = 5000
+    rng = np.random.default_rng(n_prune)
+    vals = rng.integers(0, 5, size=n).astype(np.float32) * np.float32(0.5)
+    vals[::7] = -0.0
+    vals[::11] = 0.0
+    vals[3] = np.nan
+    vals[9] = -np.float32(2.5)
+    vals[10] = np.inf
+    dev = torch.device("cuda:0")
+    s = torch.from_numpy(vals).to(dev)
+    keep = torch.empty(n, dtype=torch.uint8, device=dev)
+    nk = torch.empty(1, dtype=torch.int64, device=dev)
+    ws = api.workspace(n, 1, dev)
+    api.refine_select(s, keep, ws, n_prune=n_prune, n_keep_out=nk)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(keep.cpu().numpy(), expected_keep_from_scores(vals, n_prune))
+    assert int(nk.item()) == n - n_prune
+
+
+def test_select_all_equal_scores():
+    import torch
+
+    from paper_2606_09074_amd import api
+    n = 10007
+    dev = torch.device("cuda:0")
+    s = torch.full((n,), 0.125, dtype=torch.float32, device=dev)
+    keep = torch.empty(n, dtype=torch.uint8, device=dev)
+    ws = api.workspace(n, 1, dev)
+    api.refine_select(s, keep, ws, ratio=0.37)
+    k = api.prune_count(n, 0.37)
+    got = keep.cpu().numpy()
+    assert got[:k].sum() == 0 and got[k:].all()
+
+
+def test_compact_capacity_smaller_than_survivors():
+    import torch
+
+    from paper_2606_09074_amd import api
+    planes, _, _ = workload("small")
+    n = 9000
+    dev = torch.device("cuda:0")
+    pl = torch.from_numpy(np.ascontiguousarray(planes[:, :n])).to(dev)
+    keep_np = (np.random.default_rng(2).random(n) < 0.5).astype(np.uint8)
+    keep = torch.from_numpy(keep_np).to(dev)
+    cap = 1000
+    out = torch.full((59, cap + 5), float("nan"), dtype=torch.float32, device=dev)
+    idx = torch.full((cap + 5,), -7, dtype=torch.int32, device=dev)
+    nout = torch.empty(1, dtype=torch.int64, device=dev)
+    ws = api.workspace(n, 1, dev)
+    api.refine_compact(pl, keep, out, ws, index_map_out=idx, n_out=nout, capacity=cap)
+    torch.cuda.synchronize()
+    sel = np.nonzero(keep_np)[0]
+    assert int(nout.item()) == sel.size
+    np.testing.assert_array_equal(out.cpu().numpy()[:, :cap], planes[:, sel[:cap]])
+    np.testing.assert_array_equal(idx.cpu().numpy()[:cap], sel[:cap])
+    assert np.all(np.isnan(out.cpu().numpy()[:, cap:])) and np.all(idx.cpu().numpy()[cap:] == -7)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("ratio", [0.5, 0.9])
+def test_medium_workload_full_parity(ratio):
+    """3M primitives x 200 views: every score against the oracle."""
+    planes, cams, spec = workload("medium")
+    log(f"medium: n={spec.n} V={cams.shape[0]} ratio={ratio}")
+    key = ("medium",)
+    if key not in _ORACLE_CACHE:
+        _ORACLE_CACHE[key] = oracle_all(planes, cams)
+    F, lam, D, lo, hi = _ORACLE_CACHE[key]
+    import oracle
+    n_prune = oracle.n_prune(spec.n, ratio)
+    r = run_gpu(planes, cams, ratio=ratio)
+    check_stats(r["stats"], F, lam, "medium")
+    check_scores(r["scores"], D, lo, hi, "medium scores")
+    np.testing.assert_array_equal(r["keep"], expected_keep_from_scores(r["scores"], n_prune))
+    check_mask_vs_oracle(r["keep"], D, lo, hi, n_prune, f"medium mask beta={ratio}")
+    _check_compact(planes, spec.n, r)
+
+
+_ORACLE_CACHE = {}
+
+
+@pytest.mark.slow
+def test_large_workload_sampled_parity():
+    """6M primitives x 300 views: sampled scores against the oracle, the
+    mask against a stable sort of the GPU's own scores, compaction exact."""
+    import oracle
+    planes, cams, spec = workload("large")
+    log(f"large: n={spec.n} V={cams.shape[0]}")
+    prm = oracle_params()
+    F = oracle.stats(planes, eta=prm.eta)
+    lam = oracle.lam(F, prm)
+    idx = np.unique(np.concatenate([np.arange(0, spec.n, 29), np.arange(spec.n - 300, spec.n)]))
+    D, lo, hi, _ = oracle.score(planes, cams, lam, prm, idx=idx)
+    n_prune = oracle.n_prune(spec.n, 0.66)
+    r = run_gpu(planes, cams, ratio=0.66)
+    check_stats(r["stats"], F, lam, "large")
+    check_scores(r["scores"][idx], D, lo, hi, "large sampled scores")
+    np.testing.assert_array_equal(r["keep"], expected_keep_from_scores(r["scores"], n_prune))
+    _check_compact(planes, spec.n, r)
