@@ -46,7 +46,12 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="medium", choices=["small", "medium", "large"])
     ap.add_argument("--ratio", type=float, default=None)
+    ap.add_argument("--score-path", default="auto", choices=["auto", "direct", "binned"],
+                    help="refine_score scheduling (results are bit-identical across paths)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB (3 times) and exit: the reference "
+                         "kernel for scaling HBM traffic counters")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -64,6 +69,15 @@ def main() -> int:
     if not torch.cuda.is_available():
         log("bench.py needs a GPU")
         return 2
+    if args.copy_calibration:
+        nbytes = args.copy_calibration << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": nbytes, "copies": 3}), flush=True)
+        return 0
     spec = synth.SPECS[args.workload]
     ratio = args.ratio if args.ratio is not None else spec.ratios[0]
     log(f"bench: generating {spec.name} (n={spec.n}, V={spec.n_views}), ratio {ratio}")
@@ -75,6 +89,7 @@ def main() -> int:
     planes = torch.from_numpy(planes_np).to(dev)
     cams = torch.from_numpy(cams_np).to(dev)
     params = _lib.default_params()
+    params.score_path = {"auto": _lib.PATH_AUTO, "direct": _lib.PATH_DIRECT, "binned": _lib.PATH_BINNED}[args.score_path]
     ws = api.workspace(n, V, dev)
     st = torch.empty(_lib.STATS_BYTES, dtype=torch.uint8, device=dev)
     scores = torch.empty(n, dtype=torch.float32, device=dev)
@@ -155,7 +170,8 @@ def main() -> int:
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
             "data": "synthetic",
             "config": {"workload": spec.name, "n": n, "views": V, "ratio": ratio,
-                       "step": "stats+score+select+compact", "ms_per_prune": round(ms_per_step, 4)},
+                       "step": "stats+score+select+compact", "score_path": args.score_path,
+                       "ms_per_prune": round(ms_per_step, 4)},
             "phases_ms": {k: round(v, 4) for k, v in avg.items()},
             "roofline": roofline, "cpu_baseline": cpu}
     print(json.dumps(line), flush=True)

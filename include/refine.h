@@ -94,6 +94,13 @@ typedef struct {
  *  n_sub_views
  *           0 = every camera; m > 0 = cameras floor(j * V / m), j < m (the
  *           view subsampling of Table B.1 uses m = 64)
+ *  score_path
+ *           execution choice of refine_score, never a change of results
+ *           (every path gives bit-identical scores): REFINE_PATH_AUTO (0),
+ *           REFINE_PATH_DIRECT (1: every (primitive, view) pair evaluated in
+ *           input order) or REFINE_PATH_BINNED (2: primitives grouped by
+ *           spatial cell, (group, view) pairs whose conservative footprint
+ *           bound misses the view frustum skipped)
  */
 typedef struct {
     double eta;
@@ -106,7 +113,11 @@ typedef struct {
     int32_t vis_mode;
     int32_t equal_lambda;
     int32_t n_sub_views;
+    int32_t score_path;
+    int32_t reserved;       /* must be 0 */
 } refine_params;
+
+typedef enum { REFINE_PATH_AUTO = 0, REFINE_PATH_DIRECT = 1, REFINE_PATH_BINNED = 2 } refine_score_path;
 
 /*
  * Scene statistics written to device memory by refine_stats:
@@ -118,6 +129,8 @@ typedef struct {
  *  n_nonfinite                 primitives with a non-finite value in one of
  *                              the 14 planes the scoring reads; when > 0 the
  *                              features and scores are not meaningful
+ *  bbox_min, bbox_max          axis-aligned bounds of the finite centres
+ *                              (refine_score's spatial binning reads them)
  */
 typedef struct {
     double ybar;
@@ -127,6 +140,8 @@ typedef struct {
     double lambda[3];
     int64_t n;
     int64_t n_nonfinite;
+    float bbox_min[3];
+    float bbox_max[3];
 } refine_stats_t;
 
 /* Library version string (static storage). */
@@ -162,6 +177,7 @@ refine_status refine_stats(const refine_scene* scene, const refine_params* param
  * with the visibility V_i and projection P_i^v of the selected modes and the
  * gate g_i^v (depth > z_near and the 3-sigma footprint of the projected
  * covariance overlapping the image).  FP32 arithmetic, views summed in order.
+ * params->score_path picks how the pairs are scheduled (results identical).
  *  d_cams    device float32 [n_views][18]: world-to-camera rotation R
  *            (row-major), translation t (p_cam = R p + t), fx, fy, cx, cy,
  *            W, H (pixels; Eq. 13), camera axes x right, y down, z forward

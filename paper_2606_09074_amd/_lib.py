@@ -21,6 +21,7 @@ REFINE_E_HIP = -4
 REFINE_F32 = 0
 PROJ_COV, PROJ_DEPTH, PROJ_NONE = 0, 1, 2
 VIS_ALPHA, VIS_NONE = 0, 1
+PATH_AUTO, PATH_DIRECT, PATH_BINNED = 0, 1, 2
 
 EXPORTED = ("refine_version", "refine_status_string", "refine_params_default", "refine_prune_count",
             "refine_workspace_size", "refine_stats", "refine_score", "refine_select", "refine_compact")
@@ -35,13 +36,15 @@ class Params(ctypes.Structure):
     _fields_ = [("eta", ctypes.c_double), ("z_near", ctypes.c_double), ("clamp_k", ctypes.c_double),
                 ("e_col", ctypes.c_double), ("e_opa", ctypes.c_double), ("e_lngem", ctypes.c_double),
                 ("proj_mode", ctypes.c_int32), ("vis_mode", ctypes.c_int32),
-                ("equal_lambda", ctypes.c_int32), ("n_sub_views", ctypes.c_int32)]
+                ("equal_lambda", ctypes.c_int32), ("n_sub_views", ctypes.c_int32),
+                ("score_path", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
     _fields_ = [("ybar", ctypes.c_double), ("f_col", ctypes.c_double), ("f_opa", ctypes.c_double),
                 ("f_gem", ctypes.c_double), ("lam", ctypes.c_double * 3), ("n", ctypes.c_int64),
-                ("n_nonfinite", ctypes.c_int64)]
+                ("n_nonfinite", ctypes.c_int64), ("bbox_min", ctypes.c_float * 3),
+                ("bbox_max", ctypes.c_float * 3)]
 
 
 STATS_BYTES = ctypes.sizeof(Stats)

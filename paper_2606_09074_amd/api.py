@@ -117,7 +117,7 @@ def stats_from_tensor(stats: torch.Tensor) -> dict:
     raw = bytes(stats[:_lib.STATS_BYTES].cpu().numpy().tobytes())
     s = Stats.from_buffer_copy(raw)
     return {"ybar": s.ybar, "f_col": s.f_col, "f_opa": s.f_opa, "f_gem": s.f_gem, "lambda": list(s.lam),
-            "n": s.n, "n_nonfinite": s.n_nonfinite}
+            "n": s.n, "n_nonfinite": s.n_nonfinite, "bbox_min": list(s.bbox_min), "bbox_max": list(s.bbox_max)}
 
 
 def prune(planes: torch.Tensor, cams: torch.Tensor, ratio: float, params: Optional[Params] = None,

@@ -42,32 +42,41 @@ refine_status check_params(const refine_params* p)
     if (p->vis_mode < REFINE_VIS_ALPHA || p->vis_mode > REFINE_VIS_NONE) return REFINE_E_INVALID;
     if (p->equal_lambda != 0 && p->equal_lambda != 1) return REFINE_E_INVALID;
     if (p->n_sub_views < 0) return REFINE_E_INVALID;
+    if (p->score_path < REFINE_PATH_AUTO || p->score_path > REFINE_PATH_BINNED) return REFINE_E_INVALID;
+    if (p->reserved != 0) return REFINE_E_INVALID;
     return REFINE_OK;
 }
 
 constexpr int32_t kMaxViews = 1 << 20;
 
-refine_status check_workspace(int64_t n, int32_t n_views, const void* ws, size_t ws_bytes, Workspace* out)
+refine_status check_workspace(int64_t n, int32_t n_views, bool score, const void* ws, size_t ws_bytes,
+                              Workspace* out)
 {
-    const size_t need = workspace_layout(n, n_views, nullptr, nullptr);
+    const size_t need = workspace_layout(n, n_views, score, nullptr, nullptr);
     if (ws_bytes < need || (need > 0 && !ws)) return REFINE_E_WORKSPACE;
-    workspace_layout(n, n_views, const_cast<void*>(ws), out);
+    workspace_layout(n, n_views, score, const_cast<void*>(ws), out);
     return REFINE_OK;
 }
 
 }  // namespace
 
-size_t workspace_layout(int64_t n, int32_t n_views, void* base, Workspace* ws)
+size_t workspace_layout(int64_t n, int32_t n_views, bool score, void* base, Workspace* ws)
 {
     const size_t nt = (size_t)(num_tiles(n) > 0 ? num_tiles(n) : 1);
+    const size_t nv = (size_t)(n_views > 0 ? n_views : 0);
     size_t off = 0;
     const size_t o_sel = off;   off += align_up(sizeof(SelectState));
     const size_t o_hist = off;  off += align_up(sizeof(uint32_t) * kHistBins);
     const size_t o_part = off;  off += align_up(sizeof(double) * kStatSlots * nt);
     const size_t o_cnt = off;   off += align_up(sizeof(uint32_t) * nt);
     const size_t o_toff = off;  off += align_up(sizeof(uint32_t) * nt);
-    // the camera table is last, so calls without cameras need a prefix only
-    const size_t o_cams = off;  off += align_up(sizeof(CamRec) * (size_t)(n_views > 0 ? n_views : 0));
+    // sections only refine_score uses come last, so the other calls need a prefix only
+    const size_t o_cams = off;  off += score ? align_up(sizeof(CamRec) * nv) : 0;
+    const size_t o_cull = off;  off += score ? align_up(sizeof(CullRec) * nv) : 0;
+    const size_t o_ccnt = off;  off += score ? align_up(sizeof(uint32_t) * kCells) : 0;
+    const size_t o_ccur = off;  off += score ? align_up(sizeof(uint32_t) * kCells) : 0;
+    const size_t o_dest = off;  off += score ? align_up(sizeof(uint32_t) * (size_t)n) : 0;
+    const size_t o_recs = off;  off += score ? align_up(sizeof(PrimRec) * (size_t)n) : 0;
     if (base && ws) {
         char* b = static_cast<char*>(base);
         ws->sel = reinterpret_cast<SelectState*>(b + o_sel);
@@ -75,7 +84,12 @@ size_t workspace_layout(int64_t n, int32_t n_views, void* base, Workspace* ws)
         ws->stat_part = reinterpret_cast<double*>(b + o_part);
         ws->tile_cnt = reinterpret_cast<uint32_t*>(b + o_cnt);
         ws->tile_off = reinterpret_cast<uint32_t*>(b + o_toff);
-        ws->cams = reinterpret_cast<CamRec*>(b + o_cams);
+        ws->cams = score ? reinterpret_cast<CamRec*>(b + o_cams) : nullptr;
+        ws->culls = score ? reinterpret_cast<CullRec*>(b + o_cull) : nullptr;
+        ws->cell_cnt = score ? reinterpret_cast<uint32_t*>(b + o_ccnt) : nullptr;
+        ws->cell_cur = score ? reinterpret_cast<uint32_t*>(b + o_ccur) : nullptr;
+        ws->dest = score ? reinterpret_cast<uint32_t*>(b + o_dest) : nullptr;
+        ws->recs = score ? reinterpret_cast<PrimRec*>(b + o_recs) : nullptr;
     }
     return off;
 }
@@ -129,7 +143,7 @@ refine_status refine_workspace_size(int64_t n, int32_t n_views, size_t* bytes)
 {
     if (!bytes || n < 0 || n_views < 0) return REFINE_E_INVALID;
     if (n > (int64_t)std::numeric_limits<int32_t>::max() || n_views > kMaxViews) return REFINE_E_UNSUPPORTED;
-    *bytes = workspace_layout(n, n_views, nullptr, nullptr);
+    *bytes = workspace_layout(n, n_views, true, nullptr, nullptr);
     return REFINE_OK;
 }
 
@@ -141,7 +155,7 @@ refine_status refine_stats(const refine_scene* scene, const refine_params* param
     if ((s = check_params(params)) != REFINE_OK) return s;
     if (!d_stats) return REFINE_E_INVALID;
     Workspace ws;
-    if ((s = check_workspace(scene->n, 0, d_ws, ws_bytes, &ws)) != REFINE_OK) return s;
+    if ((s = check_workspace(scene->n, 0, false, d_ws, ws_bytes, &ws)) != REFINE_OK) return s;
     const hipError_t e = launch_stats(static_cast<const float*>(scene->planes), scene->stride, scene->n, *params,
                                       d_stats, ws, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? REFINE_OK : REFINE_E_HIP;
@@ -158,7 +172,7 @@ refine_status refine_score(const refine_scene* scene, const float* d_cams, int32
     if (n_views > kMaxViews) return REFINE_E_UNSUPPORTED;
     if (scene->n > 0 && !d_scores) return REFINE_E_INVALID;
     Workspace ws;
-    if ((s = check_workspace(scene->n, n_views, d_ws, ws_bytes, &ws)) != REFINE_OK) return s;
+    if ((s = check_workspace(scene->n, n_views, true, d_ws, ws_bytes, &ws)) != REFINE_OK) return s;
     const hipError_t e = launch_score(static_cast<const float*>(scene->planes), scene->stride, scene->n, d_cams,
                                       n_views, *params, d_stats, d_scores, ws, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? REFINE_OK : REFINE_E_HIP;
@@ -180,7 +194,7 @@ refine_status refine_select(const float* d_scores, int64_t n, double ratio, int6
         if (n_prune < 0) return REFINE_E_INVALID;
     }
     Workspace ws;
-    refine_status s = check_workspace(n, 0, d_ws, ws_bytes, &ws);
+    refine_status s = check_workspace(n, 0, false, d_ws, ws_bytes, &ws);
     if (s != REFINE_OK) return s;
     const hipError_t e = launch_select(d_scores, n, n_prune, d_keep, d_n_keep, d_threshold, ws,
                                        static_cast<hipStream_t>(stream));
@@ -203,7 +217,7 @@ refine_status refine_compact(const refine_scene* in, const uint8_t* d_keep, cons
         if (a0 < b1 && b0 < a1) return REFINE_E_INVALID;
     }
     Workspace ws;
-    if ((s = check_workspace(in->n, 0, d_ws, ws_bytes, &ws)) != REFINE_OK) return s;
+    if ((s = check_workspace(in->n, 0, false, d_ws, ws_bytes, &ws)) != REFINE_OK) return s;
     const hipError_t e = launch_compact(static_cast<const float*>(in->planes), in->stride, in->n, d_keep,
                                         static_cast<float*>(out->planes), out->stride, out->n, d_index_map, d_n_out,
                                         ws, static_cast<hipStream_t>(stream));

@@ -22,18 +22,18 @@ constexpr int kHistBits = 11;
 constexpr int kHistBins = 1 << kHistBits;
 constexpr int kStatSlots = 8;      // doubles per stats partial
 
-// Prepared camera record (fp32, 128 bytes), built by camera_prep.
+// Prepared camera record (fp32, 128 bytes), built by camera_prep.  Pixel
+// quantities are scaled by sv = 1 / sqrt(fx^2 + fy^2): the gate is invariant
+// under that scaling and the projection term of mode COV becomes
+// (a + c) / (z^2 + eta) with no per-camera factor.
 struct CamRec {
-    float r[9];        // world-to-camera rotation, rows
-    float t[3];
-    float fr0[3];      // fx * row 0
-    float fr1[3];      // fy * row 1
-    float fx, fy;
-    float ox, oy;      // cx - W/2, cy - H/2
-    float hw, hh;      // W/2, H/2
-    float lx, ly;      // clamp_k * W/2, clamp_k * H/2 (pixels)
-    float kv;          // 1 / (fx^2 + fy^2)
-    float pad[5];
+    float px[4];       // sv fx R_v row 0, sv fx t_x   -> X = sv fx x
+    float py[4];       // sv fy R_v row 1, sv fy t_y   -> Y = sv fy y
+    float pz[4];       // R_v row 2, t_z               -> z
+    float ox, oy;      // sv (cx - W/2), sv (cy - H/2)
+    float hw, hh;      // sv W/2, sv H/2
+    float lx, ly;      // sv clamp_k W/2, sv clamp_k H/2
+    float pad[14];
 };
 static_assert(sizeof(CamRec) == kCamRec * sizeof(float), "camera record size");
 
@@ -50,19 +50,52 @@ struct SelectState {
     uint32_t pad[7];
 };
 
+// Conservative view-frustum test data of one view (fp32, 128 bytes): the
+// world-space half-spaces every visible primitive's centre must satisfy,
+// given a bound on its footprint radius.  Built by camera_prep.
+struct CullRec {
+    float nz[4];        // R_v row 2, t_z: depth = nz . mu + nz[3]
+    float side[4][4];   // per image edge: n (3), d; visible => n . mu + d + 3 s_max kv > 0
+    float nn[4];        // |n| of each side
+    float kv3;          // 3 (1 + margin) sqrt(fx^2 (1 + lim_x^2) + fy^2 (1 + lim_y^2))
+    float pad[7];
+};
+static_assert(sizeof(CullRec) == 32 * sizeof(float), "cull record size");
+
+// Activated primitive in binned order (64 bytes), written by bin_scatter.
+struct PrimRec {
+    float mu[3];
+    float L[9];        // R(q) diag(s), row-major
+    float pre;         // epilogue factor V K / (|V| [sbar^2])
+    float smax;        // largest scale
+    int32_t idx;       // input index
+    float pad;
+};
+static_assert(sizeof(PrimRec) == 64, "primitive record size");
+
+constexpr int kCellBits = 4;                       // per axis
+constexpr int kCells = 1 << (3 * kCellBits);       // 4096 Morton cells
+
 struct Workspace {
     SelectState* sel;
     uint32_t* hist;          // [kHistBins]
     double* stat_part;       // [ntiles][kStatSlots]
     uint32_t* tile_cnt;      // [ntiles]
     uint32_t* tile_off;      // [ntiles]
+    // refine_score only:
     CamRec* cams;            // [n_views]
+    CullRec* culls;          // [n_views]
+    uint32_t* cell_cnt;      // [kCells]
+    uint32_t* cell_cur;      // [kCells]
+    uint32_t* dest;          // [n] binned position of each primitive
+    PrimRec* recs;           // [n]
 };
 
 inline int64_t num_tiles(int64_t n) { return (n + kTile - 1) / kTile; }
 
-// Bytes of a workspace for (n, n_views); fills *ws when base != nullptr.
-size_t workspace_layout(int64_t n, int32_t n_views, void* base, Workspace* ws);
+// Bytes of a workspace for (n, n_views); fills *ws when base != nullptr.  With
+// score == false only the prefix used by stats/select/compact is counted.
+size_t workspace_layout(int64_t n, int32_t n_views, bool score, void* base, Workspace* ws);
 
 // Launchers (validated arguments; return the hipGetLastError of the launch).
 hipError_t launch_stats(const float* planes, int64_t stride, int64_t n, const refine_params& prm,
@@ -85,6 +118,20 @@ __device__ inline double wave_sum(double v)
 {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ inline float wave_min(float v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ inline float wave_max(float v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
     return v;
 }
 

@@ -1,26 +1,46 @@
 // Rendering-free importance scores (paper Eq. 7-20) on gfx950.
 //
-// camera_prep: one thread per (possibly subsampled) view builds a 128-byte
-// fp32 record of the constants the view loop needs.
+// camera_prep: one thread per (possibly subsampled) view builds two 128-byte
+// fp32 records: the constants of the per-pair evaluation (every pixel
+// quantity scaled by sv = 1/sqrt(fx^2 + fy^2): the gate is scale invariant
+// and the projection term's 1/(fx^2 + fy^2) becomes 1), and the world-space
+// frustum half-spaces of the conservative culling test.
 //
-// score_views: one primitive per lane.  The prologue activates the primitive
-// (Eq. 1 readings) and keeps its centre mu and the factored 3D covariance
-// L = R(q) diag(s) (Sigma = L L^T) in VGPRs for the whole view loop.  Camera
-// records are read through the scalar cache (the index is wave-uniform), so
-// the loop body is pure VALU work.  Per (primitive, view), in FP32:
-//   p = R_v mu + t_v                               camera-space centre
-//   ux = fx x/z, uy = fy y/z                        Eq. 13 about the principal point
-//   x^ = clamp(ux, +-k W/2), y^ = clamp(uy, +-k H/2) clamped, in pixels
-//   r0 = fx R_v,0 - x^ R_v,2,  r1 = fy R_v,1 - y^ R_v,2
-//       so that the EWA Jacobian times the view rotation is [r0; r1] / z (Eq. 14)
-//   A0 = r0 L, A1 = r1 L;  a = |A0|^2, b = A0.A1, c = |A1|^2
-//       z^2 Sigma' = [[a, b], [b, c]]: sums of squares, free of the
-//       cancellation that T Sigma T^T suffers for needle-like primitives
-//   gate: z > z_near and the 3-sigma box of Sigma' overlaps the image
-//   projection term (mode COV): (a + c) / ((fx^2 + fy^2) (z^2 + eta)), the
-//       1/sbar^2 factor being applied once in the epilogue
-// The views are accumulated in order into one FP32 sum per primitive; the
-// epilogue forms D = V K S / |V| (Eq. 20 then Eq. 7).
+// Per (primitive, view) pair, FP32 (eval_pair; identical in both paths):
+//   X = sv fx x, Y = sv fy y, z       camera-space centre (Eq. 13 numerators)
+//   q = 1/(z (z^2 + eta)):  1/z = q (z^2 + eta),  1/(z^2 + eta) = q z
+//   ux = X/z, uy = Y/z                projected centre about the principal point
+//   x^ = clamp(ux, +-lx), y^ = clamp(uy, +-ly)   EWA clamp (scaled pixels)
+//   r0 = sv fx R_v,0 - x^ R_v,2,  r1 = sv fy R_v,1 - y^ R_v,2
+//       [r0; r1] / z is the scaled EWA Jacobian times the view rotation (Eq. 14)
+//   A0 = r0 L, A1 = r1 L with L = R(q) diag(s);  a = |A0|^2, b = A0.A1, c = |A1|^2
+//       z^2 Sigma' = [[a, b], [b, c]] as sums of squares (no cancellation for
+//       needle-like primitives, unlike T Sigma T^T in FP32)
+//   gate: z > z_near, and the centre lies within the 3-sigma radius
+//       r = 3 sqrt(lambda_max(Sigma')) of the image rectangle; with
+//       d = max(|ux + ox| - hw, |uy + oy| - hh) the test d < r reads
+//       d z < 0  or  (d z)^2 < 4.5 (a + c + sqrt((a - c)^2 + 4 b^2))
+//   projection term: COV (a + c)/(z^2 + eta) (1/sbar^2 applied in the
+//       epilogue), DEPTH 1/(z^2 + eta) (Eq. 17), NONE 1
+// Views are accumulated in view order into one FP32 sum per primitive; the
+// epilogue forms D = V K S / |V| (Eq. 20, then Eq. 7).
+//
+// Direct path (score_direct): one primitive per lane in input order, every
+// pair evaluated.
+//
+// Binned path: bin_hist / bin_scan / bin_scatter counting-sort the primitives
+// by the Morton code of a 16^3 grid over the centres' bounding box (per-tile
+// LDS histograms, so a crowded cell costs one global atomic per tile, not
+// per primitive) and write each activated primitive as a 64-byte record in
+// cell order.  score_binned
+// then gives each wave 64 spatially close primitives: the wave bounds them by
+// a sphere (centre c, radius R) and by their largest scale s_max; each lane
+// tests one view against the sphere, and the ballot of the results is the
+// set of views the wave evaluates.  A view is skipped only when no point of
+// the sphere can pass the near plane or one image edge even with the largest
+// footprint any of its primitives can have, r <= 3 s_max |J|_F (the clamp
+// bounds |J|_F z by kv), inflated by a 1% margin: every skipped pair would
+// have added exactly +0, so both paths give bit-identical scores.
 #include "refine_internal.hpp"
 
 namespace refine {
@@ -28,54 +48,87 @@ namespace refine {
 namespace {
 
 constexpr float kShC0 = 0.28209479177387814f;
+constexpr float kCullMargin = 1.01f;
+constexpr int64_t kBinnedMinPrims = 65536;
 
 __global__ __launch_bounds__(kBlock) void camera_prep(const float* __restrict__ cams, int n_views, int nv,
-                                                        float clamp_k, CamRec* __restrict__ out)
+                                                        float clamp_k, CamRec* __restrict__ out,
+                                                        CullRec* __restrict__ cull)
 {
     const int j = blockIdx.x * kBlock + threadIdx.x;
     if (j >= nv) return;
     const int v = (nv == n_views) ? j : (int)(((int64_t)j * n_views) / nv);
     const float* c = cams + (int64_t)v * kCamFields;
+    const float fx = c[12], fy = c[13], cx = c[14], cy = c[15], W = c[16], H = c[17];
+    const float sv = rsqrtf(fx * fx + fy * fy);
+    const float sx = sv * fx, sy = sv * fy;
     CamRec r;
 #pragma unroll
-    for (int k = 0; k < 9; ++k) r.r[k] = c[k];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) r.t[k] = c[9 + k];
-    const float fx = c[12], fy = c[13], cx = c[14], cy = c[15], W = c[16], H = c[17];
-#pragma unroll
     for (int k = 0; k < 3; ++k) {
-        r.fr0[k] = fx * c[k];
-        r.fr1[k] = fy * c[3 + k];
+        r.px[k] = sx * c[k];
+        r.py[k] = sy * c[3 + k];
+        r.pz[k] = c[6 + k];
     }
-    r.fx = fx;
-    r.fy = fy;
-    r.hw = 0.5f * W;
-    r.hh = 0.5f * H;
-    r.ox = cx - r.hw;
-    r.oy = cy - r.hh;
+    r.px[3] = sx * c[9];
+    r.py[3] = sy * c[10];
+    r.pz[3] = c[11];
+    r.hw = sv * (0.5f * W);
+    r.hh = sv * (0.5f * H);
+    r.ox = sv * (cx - 0.5f * W);
+    r.oy = sv * (cy - 0.5f * H);
     r.lx = clamp_k * r.hw;
     r.ly = clamp_k * r.hh;
-    r.kv = 1.0f / (fx * fx + fy * fy);
 #pragma unroll
-    for (int k = 0; k < 5; ++k) r.pad[k] = 0.0f;
+    for (int k = 0; k < 14; ++k) r.pad[k] = 0.0f;
     out[j] = r;
+
+    // culling half-spaces: u + r > 0, W - u + r > 0, v + r > 0, H - v + r > 0,
+    // multiplied by z > 0 and written as n . mu + d + r z > 0 with r z <= 3 s_max kv
+    CullRec q;
+    const float* R0 = c;
+    const float* R1 = c + 3;
+    const float* R2 = c + 6;
+    const float tx = c[9], ty = c[10], tz = c[11];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        q.nz[k] = R2[k];
+        q.side[0][k] = fx * R0[k] + cx * R2[k];
+        q.side[1][k] = (W - cx) * R2[k] - fx * R0[k];
+        q.side[2][k] = fy * R1[k] + cy * R2[k];
+        q.side[3][k] = (H - cy) * R2[k] - fy * R1[k];
+    }
+    q.nz[3] = tz;
+    q.side[0][3] = fx * tx + cx * tz;
+    q.side[1][3] = (W - cx) * tz - fx * tx;
+    q.side[2][3] = fy * ty + cy * tz;
+    q.side[3][3] = (H - cy) * tz - fy * ty;
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+        q.nn[s] = sqrtf(q.side[s][0] * q.side[s][0] + q.side[s][1] * q.side[s][1] + q.side[s][2] * q.side[s][2]);
+    const float limx = clamp_k * W / (2.0f * fx), limy = clamp_k * H / (2.0f * fy);
+    q.kv3 = 3.0f * kCullMargin * sqrtf(fx * fx * (1.0f + limx * limx) + fy * fy * (1.0f + limy * limy));
+#pragma unroll
+    for (int k = 0; k < 7; ++k) q.pad[k] = 0.0f;
+    cull[j] = q;
 }
 
-// PROJ: refine_proj_mode
-template <int PROJ>
-__global__ __launch_bounds__(kBlock) void score_views(const float* __restrict__ planes, int64_t stride, int n,
-                                                        const CamRec* __restrict__ cams, int nv,
-                                                        const refine_stats_t* __restrict__ st, float eta,
-                                                        float z_near, int vis_alpha, float* __restrict__ out)
+// Registers a lane keeps for one primitive across the view loop.
+struct Prim {
+    float mx, my, mz;
+    float L00, L01, L02, L10, L11, L12, L20, L21, L22;
+    float S;
+};
+
+// Activation (Sec. 3.1 readings) of primitive i; pre is the epilogue factor.
+__device__ inline void activate(const float* __restrict__ planes, int64_t stride, int i, Prim& p, float& pre,
+                                float& smax, const refine_stats_t* __restrict__ st, int proj, int vis_alpha, int nv)
 {
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
     float a[kScorePlanes];
 #pragma unroll
-    for (int p = 0; p < kScorePlanes; ++p) a[p] = planes[(int64_t)p * stride + i];
-
-    // ---- activation (Sec. 3.1): s = exp(log-scale), unit quaternion, alpha = sigmoid(logit)
-    const float mx = a[0], my = a[1], mz = a[2];
+    for (int k = 0; k < kScorePlanes; ++k) a[k] = planes[(int64_t)k * stride + i];
+    p.mx = a[0];
+    p.my = a[1];
+    p.mz = a[2];
     const float s0 = __expf(a[3]), s1 = __expf(a[4]), s2 = __expf(a[5]);
     float qw = a[6], qx = a[7], qy = a[8], qz = a[9];
     const float qn = qw * qw + qx * qx + qy * qy + qz * qz;
@@ -85,70 +138,274 @@ __global__ __launch_bounds__(kBlock) void score_views(const float* __restrict__ 
     } else {
         qw = 1.0f; qx = qy = qz = 0.0f;
     }
-    // L = R(q) diag(s)
-    const float L00 = (1.0f - 2.0f * (qy * qy + qz * qz)) * s0;
-    const float L01 = (2.0f * (qx * qy - qw * qz)) * s1;
-    const float L02 = (2.0f * (qx * qz + qw * qy)) * s2;
-    const float L10 = (2.0f * (qx * qy + qw * qz)) * s0;
-    const float L11 = (1.0f - 2.0f * (qx * qx + qz * qz)) * s1;
-    const float L12 = (2.0f * (qy * qz - qw * qx)) * s2;
-    const float L20 = (2.0f * (qx * qz - qw * qy)) * s0;
-    const float L21 = (2.0f * (qy * qz + qw * qx)) * s1;
-    const float L22 = (1.0f - 2.0f * (qx * qx + qy * qy)) * s2;
-
+    p.L00 = (1.0f - 2.0f * (qy * qy + qz * qz)) * s0;
+    p.L01 = (2.0f * (qx * qy - qw * qz)) * s1;
+    p.L02 = (2.0f * (qx * qz + qw * qy)) * s2;
+    p.L10 = (2.0f * (qx * qy + qw * qz)) * s0;
+    p.L11 = (1.0f - 2.0f * (qx * qx + qz * qz)) * s1;
+    p.L12 = (2.0f * (qy * qz - qw * qx)) * s2;
+    p.L20 = (2.0f * (qx * qz - qw * qy)) * s0;
+    p.L21 = (2.0f * (qy * qz + qw * qx)) * s1;
+    p.L22 = (1.0f - 2.0f * (qx * qx + qy * qy)) * s2;
+    p.S = 0.0f;
+    smax = fmaxf(s0, fmaxf(s1, s2));
     const float sbar2 = (s0 * s0 + s1 * s1 + s2 * s2) * (1.0f / 3.0f);
     const float alpha = 1.0f / (1.0f + __expf(-a[10]));
     const float cr = fmaf(kShC0, a[11], 0.5f), cg = fmaf(kShC0, a[12], 0.5f), cb = fmaf(kShC0, a[13], 0.5f);
-    // attribute magnitudes (Eq. 7): two largest scales' product, |colour|, alpha
+    // attribute magnitudes G~ (Eq. 7): two largest scales' product, |DC colour|, alpha
     const float g_gem = fmaxf(s0 * s1, fmaxf(s0 * s2, s1 * s2));
     const float g_col = sqrtf(cr * cr + cg * cg + cb * cb);
     const float K = (float)st->lambda[0] * g_gem + (float)st->lambda[1] * g_col + (float)st->lambda[2] * alpha;
+    pre = (vis_alpha ? alpha : 1.0f) * K / (float)nv;
+    if (proj == REFINE_PROJ_COV) pre = pre / sbar2;
+}
 
-    // ---- view loop (Eq. 20)
-    float S = 0.0f;
-    for (int v = 0; v < nv; ++v) {
-        const CamRec& c = cams[v];
-        const float x = fmaf(c.r[0], mx, fmaf(c.r[1], my, fmaf(c.r[2], mz, c.t[0])));
-        const float y = fmaf(c.r[3], mx, fmaf(c.r[4], my, fmaf(c.r[5], mz, c.t[1])));
-        const float z = fmaf(c.r[6], mx, fmaf(c.r[7], my, fmaf(c.r[8], mz, c.t[2])));
-        const float rz = __builtin_amdgcn_rcpf(z);
-        const float ux = c.fx * x * rz;
-        const float uy = c.fy * y * rz;
-        const float xh = fminf(fmaxf(ux, -c.lx), c.lx);
-        const float yh = fminf(fmaxf(uy, -c.ly), c.ly);
-        const float r00 = fmaf(-xh, c.r[6], c.fr0[0]);
-        const float r01 = fmaf(-xh, c.r[7], c.fr0[1]);
-        const float r02 = fmaf(-xh, c.r[8], c.fr0[2]);
-        const float r10 = fmaf(-yh, c.r[6], c.fr1[0]);
-        const float r11 = fmaf(-yh, c.r[7], c.fr1[1]);
-        const float r12 = fmaf(-yh, c.r[8], c.fr1[2]);
-        const float A00 = fmaf(r00, L00, fmaf(r01, L10, r02 * L20));
-        const float A01 = fmaf(r00, L01, fmaf(r01, L11, r02 * L21));
-        const float A02 = fmaf(r00, L02, fmaf(r01, L12, r02 * L22));
-        const float A10 = fmaf(r10, L00, fmaf(r11, L10, r12 * L20));
-        const float A11 = fmaf(r10, L01, fmaf(r11, L11, r12 * L21));
-        const float A12 = fmaf(r10, L02, fmaf(r11, L12, r12 * L22));
-        const float sa = fmaf(A00, A00, fmaf(A01, A01, A02 * A02));
-        const float sc = fmaf(A10, A10, fmaf(A11, A11, A12 * A12));
-        const float sb = fmaf(A00, A10, fmaf(A01, A11, A02 * A12));
-        // 3-sigma footprint: r = 3 sqrt(lambda_max) / z, lambda_max of [[sa, sb], [sb, sc]]
-        const float hm = 0.5f * (sa - sc);
-        const float lmax = fmaf(0.5f, sa + sc, sqrtf(fmaf(hm, hm, sb * sb)));
-        const float rad = 3.0f * sqrtf(lmax) * rz;
-        const float d = fmaxf(fabsf(ux + c.ox) - c.hw, fabsf(uy + c.oy) - c.hh);
-        const bool g = (z > z_near) && (d < rad);
-        float P;
-        if (PROJ == REFINE_PROJ_COV)
-            P = c.kv * (sa + sc) * __builtin_amdgcn_rcpf(fmaf(z, z, eta));
-        else if (PROJ == REFINE_PROJ_DEPTH)
-            P = __builtin_amdgcn_rcpf(fmaf(z, z, eta));
-        else
-            P = 1.0f;
-        S += g ? P : 0.0f;
+template <int PROJ>
+__device__ __forceinline__ void eval_pair(const CamRec& c, Prim& p, float eta, float z_near)
+{
+    const float X = fmaf(c.px[0], p.mx, fmaf(c.px[1], p.my, fmaf(c.px[2], p.mz, c.px[3])));
+    const float Y = fmaf(c.py[0], p.mx, fmaf(c.py[1], p.my, fmaf(c.py[2], p.mz, c.py[3])));
+    const float z = fmaf(c.pz[0], p.mx, fmaf(c.pz[1], p.my, fmaf(c.pz[2], p.mz, c.pz[3])));
+    const float zz = fmaf(z, z, eta);
+    const float q = __builtin_amdgcn_rcpf(z * zz);
+    const float rz = q * zz;
+    const float ux = X * rz;
+    const float uy = Y * rz;
+    const float xh = __builtin_amdgcn_fmed3f(ux, -c.lx, c.lx);
+    const float yh = __builtin_amdgcn_fmed3f(uy, -c.ly, c.ly);
+    const float r00 = fmaf(-xh, c.pz[0], c.px[0]);
+    const float r01 = fmaf(-xh, c.pz[1], c.px[1]);
+    const float r02 = fmaf(-xh, c.pz[2], c.px[2]);
+    const float r10 = fmaf(-yh, c.pz[0], c.py[0]);
+    const float r11 = fmaf(-yh, c.pz[1], c.py[1]);
+    const float r12 = fmaf(-yh, c.pz[2], c.py[2]);
+    const float A00 = fmaf(r00, p.L00, fmaf(r01, p.L10, r02 * p.L20));
+    const float A01 = fmaf(r00, p.L01, fmaf(r01, p.L11, r02 * p.L21));
+    const float A02 = fmaf(r00, p.L02, fmaf(r01, p.L12, r02 * p.L22));
+    const float A10 = fmaf(r10, p.L00, fmaf(r11, p.L10, r12 * p.L20));
+    const float A11 = fmaf(r10, p.L01, fmaf(r11, p.L11, r12 * p.L21));
+    const float A12 = fmaf(r10, p.L02, fmaf(r11, p.L12, r12 * p.L22));
+    const float sa = fmaf(A00, A00, fmaf(A01, A01, A02 * A02));
+    const float sc = fmaf(A10, A10, fmaf(A11, A11, A12 * A12));
+    const float sb = fmaf(A00, A10, fmaf(A01, A11, A02 * A12));
+    const float ss = sa + sc;
+    float P;
+    if (PROJ == REFINE_PROJ_COV)
+        P = ss * (q * z);
+    else if (PROJ == REFINE_PROJ_DEPTH)
+        P = q * z;
+    else
+        P = 1.0f;
+    const float d = fmaxf(fabsf(ux + c.ox) - c.hw, fabsf(uy + c.oy) - c.hh);
+    const float dz = d * z;
+    const float e1 = sa - sc;
+    const float w = ss + __builtin_amdgcn_sqrtf(fmaf(e1, e1, 4.0f * sb * sb));
+    const bool g = (z > z_near) && ((dz < 0.0f) || (fmaf(w, -4.5f, dz * dz) < 0.0f));
+    p.S += g ? P : 0.0f;
+}
+
+template <int PROJ>
+__global__ __launch_bounds__(kBlock) void score_direct(const float* __restrict__ planes, int64_t stride, int n,
+                                                         const CamRec* __restrict__ cams, int nv,
+                                                         const refine_stats_t* __restrict__ st, float eta,
+                                                         float z_near, int vis_alpha, float* __restrict__ out)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    Prim p;
+    float pre, smax;
+    activate(planes, stride, i, p, pre, smax, st, PROJ, vis_alpha, nv);
+    for (int v = 0; v < nv; ++v) eval_pair<PROJ>(cams[v], p, eta, z_near);
+    out[i] = pre * p.S;
+}
+
+// ------------------------------------------------------------- binned path
+
+__device__ inline uint32_t spread_bits(uint32_t x)
+{
+    // the low kCellBits bits of x moved to every third bit
+    uint32_t r = 0;
+#pragma unroll
+    for (int b = 0; b < kCellBits; ++b) r |= ((x >> b) & 1u) << (3 * b);
+    return r;
+}
+
+// Morton cell of a centre in the kCells-cell grid over the centres' box.
+__device__ inline uint32_t cell_of(float x, float y, float z, const refine_stats_t* __restrict__ st)
+{
+    const float k = (float)(1 << kCellBits);
+    const float in[3] = {x, y, z};
+    uint32_t q[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float lo = st->bbox_min[a], span = st->bbox_max[a] - lo;
+        const float t = span > 0.0f ? (in[a] - lo) * (k / span) : 0.0f;
+        q[a] = (uint32_t)fminf(fmaxf(t, 0.0f), k - 1.0f);   // NaN -> 0
     }
-    float pre = (vis_alpha ? alpha : 1.0f) * K / (float)nv;
-    if (PROJ == REFINE_PROJ_COV) pre = pre / sbar2;
-    out[i] = pre * S;
+    return spread_bits(q[0]) | (spread_bits(q[1]) << 1) | (spread_bits(q[2]) << 2);
+}
+
+__global__ __launch_bounds__(kBlock) void bin_zero(uint32_t* __restrict__ cnt)
+{
+    const int c = blockIdx.x * kBlock + threadIdx.x;
+    if (c < kCells) cnt[c] = 0u;
+}
+
+// Cell histogram: per tile in LDS, then one global add per (tile, cell).
+__global__ __launch_bounds__(kBlock) void bin_hist(const float* __restrict__ planes, int64_t stride, int n,
+                                                     const refine_stats_t* __restrict__ st,
+                                                     uint32_t* __restrict__ cnt)
+{
+    __shared__ uint32_t h[kCells];
+    for (int c = threadIdx.x; c < kCells; c += kBlock) h[c] = 0u;
+    __syncthreads();
+    const int base = blockIdx.x * kTile;
+#pragma unroll 4
+    for (int k = 0; k < kItems; ++k) {
+        const int i = base + k * kBlock + (int)threadIdx.x;
+        if (i < n) atomicAdd(&h[cell_of(planes[i], planes[stride + i], planes[2 * stride + i], st)], 1u);
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < kCells; c += kBlock)
+        if (h[c]) atomicAdd(&cnt[c], h[c]);
+}
+
+__global__ __launch_bounds__(kScanThreads) void bin_scan(const uint32_t* __restrict__ cnt, uint32_t* __restrict__ cur)
+{
+    block_exclusive_scan(cnt, cur, kCells);
+}
+
+// Counting-sort ranks: each tile reserves one output range per cell with a
+// single global atomic; its primitives take consecutive slots inside it.
+__global__ __launch_bounds__(kBlock) void bin_rank(const float* __restrict__ planes, int64_t stride, int n,
+                                                     const refine_stats_t* __restrict__ st, uint32_t* __restrict__ cur,
+                                                     uint32_t* __restrict__ dest)
+{
+    __shared__ uint32_t h[kCells];
+    for (int c = threadIdx.x; c < kCells; c += kBlock) h[c] = 0u;
+    __syncthreads();
+    const int base = blockIdx.x * kTile;
+    uint32_t cell[kItems], rank[kItems];
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        const int i = base + k * kBlock + (int)threadIdx.x;
+        cell[k] = 0u;
+        rank[k] = 0u;
+        if (i < n) {
+            cell[k] = cell_of(planes[i], planes[stride + i], planes[2 * stride + i], st);
+            rank[k] = atomicAdd(&h[cell[k]], 1u);
+        }
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < kCells; c += kBlock)
+        if (h[c]) h[c] = atomicAdd(&cur[c], h[c]);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        const int i = base + k * kBlock + (int)threadIdx.x;
+        if (i < n) dest[i] = h[cell[k]] + rank[k];
+    }
+}
+
+// Activated primitives written as records at their binned positions.
+template <int PROJ>
+__global__ __launch_bounds__(kBlock) void bin_scatter(const float* __restrict__ planes, int64_t stride, int n,
+                                                        const refine_stats_t* __restrict__ st, int vis_alpha, int nv,
+                                                        const uint32_t* __restrict__ dest, PrimRec* __restrict__ recs)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    Prim p;
+    float pre, smax;
+    activate(planes, stride, i, p, pre, smax, st, PROJ, vis_alpha, nv);
+    const uint32_t pos = dest[i];
+    PrimRec r;
+    r.mu[0] = p.mx; r.mu[1] = p.my; r.mu[2] = p.mz;
+    r.L[0] = p.L00; r.L[1] = p.L01; r.L[2] = p.L02;
+    r.L[3] = p.L10; r.L[4] = p.L11; r.L[5] = p.L12;
+    r.L[6] = p.L20; r.L[7] = p.L21; r.L[8] = p.L22;
+    r.pre = pre;
+    r.smax = smax;
+    r.idx = i;
+    r.pad = 0.0f;
+    if (pos < (uint32_t)n) recs[pos] = r;   // always true: the ranks are a permutation of [0, n)
+}
+
+// May any primitive of the wave's sphere be visible in this view?
+__device__ inline bool cull_pass(const CullRec& q, float cx, float cy, float cz, float rm, float sg, float ca,
+                                 float z_near)
+{
+    const float depth = fmaf(q.nz[0], cx, fmaf(q.nz[1], cy, fmaf(q.nz[2], cz, q.nz[3])));
+    bool ok = depth + rm + 1e-4f * (ca + fabsf(q.nz[3])) > z_near;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const float val = fmaf(q.side[s][0], cx, fmaf(q.side[s][1], cy, fmaf(q.side[s][2], cz, q.side[s][3])));
+        const float slack = 1e-4f * (q.nn[s] * (ca + 1.0f) + fabsf(q.side[s][3]));
+        ok = ok && (val + rm * q.nn[s] + sg * q.kv3 + slack > 0.0f);
+    }
+    return ok;
+}
+
+template <int PROJ>
+__global__ __launch_bounds__(kBlock) void score_binned(const PrimRec* __restrict__ recs, int n,
+                                                         const CamRec* __restrict__ cams,
+                                                         const CullRec* __restrict__ culls, int nv, float eta,
+                                                         float z_near, float* __restrict__ out)
+{
+    const int j = blockIdx.x * kBlock + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const PrimRec r = recs[min(j, n - 1)];   // lanes past the end repeat the last record
+    Prim p;
+    p.mx = r.mu[0]; p.my = r.mu[1]; p.mz = r.mu[2];
+    p.L00 = r.L[0]; p.L01 = r.L[1]; p.L02 = r.L[2];
+    p.L10 = r.L[3]; p.L11 = r.L[4]; p.L12 = r.L[5];
+    p.L20 = r.L[6]; p.L21 = r.L[7]; p.L22 = r.L[8];
+    p.S = 0.0f;
+    // bounding sphere of the wave's centres and its largest scale
+    const float cx = 0.5f * (wave_min(p.mx) + wave_max(p.mx));
+    const float cy = 0.5f * (wave_min(p.my) + wave_max(p.my));
+    const float cz = 0.5f * (wave_min(p.mz) + wave_max(p.mz));
+    const float dx = p.mx - cx, dy = p.my - cy, dz = p.mz - cz;
+    const float ca = fabsf(cx) + fabsf(cy) + fabsf(cz);
+    const float rm = sqrtf(wave_max(dx * dx + dy * dy + dz * dz)) * kCullMargin + 1e-4f * (ca + 1.0f);
+    const float sg = wave_max(r.smax);
+    // a non-finite bound (non-finite input) disables culling for this wave
+    const bool no_cull = !(rm < INFINITY) || !(sg < INFINITY) || !(ca < INFINITY);
+    for (int v0 = 0; v0 < nv; v0 += 64) {
+        const int v = v0 + lane;
+        bool vis = false;
+        if (v < nv) vis = no_cull || cull_pass(culls[v], cx, cy, cz, rm, sg, ca, z_near);
+        uint64_t m = __ballot(vis);
+        while (m) {
+            const int b = __builtin_ctzll(m);
+            m &= m - 1;
+            eval_pair<PROJ>(cams[v0 + b], p, eta, z_near);
+        }
+    }
+    if (j < n) out[r.idx] = r.pre * p.S;
+}
+
+template <int PROJ>
+void launch_mode(const float* planes, int64_t stride, int n, const refine_params& prm, const refine_stats_t* d_stats,
+                 float* d_scores, const Workspace& ws, int nv, bool binned, hipStream_t stream)
+{
+    const int vis = prm.vis_mode == REFINE_VIS_ALPHA ? 1 : 0;
+    const float eta = (float)prm.eta, zn = (float)prm.z_near;
+    const dim3 grid((unsigned)((n + kBlock - 1) / kBlock));
+    if (!binned) {
+        hipLaunchKernelGGL((score_direct<PROJ>), grid, dim3(kBlock), 0, stream, planes, stride, n, ws.cams, nv, d_stats,
+                           eta, zn, vis, d_scores);
+        return;
+    }
+    const dim3 tiles((unsigned)num_tiles(n));
+    hipLaunchKernelGGL(bin_zero, dim3(kCells / kBlock), dim3(kBlock), 0, stream, ws.cell_cnt);
+    hipLaunchKernelGGL(bin_hist, tiles, dim3(kBlock), 0, stream, planes, stride, n, d_stats, ws.cell_cnt);
+    hipLaunchKernelGGL(bin_scan, dim3(1), dim3(kScanThreads), 0, stream, ws.cell_cnt, ws.cell_cur);
+    hipLaunchKernelGGL(bin_rank, tiles, dim3(kBlock), 0, stream, planes, stride, n, d_stats, ws.cell_cur, ws.dest);
+    hipLaunchKernelGGL((bin_scatter<PROJ>), grid, dim3(kBlock), 0, stream, planes, stride, n, d_stats, vis, nv, ws.dest,
+                       ws.recs);
+    hipLaunchKernelGGL((score_binned<PROJ>), grid, dim3(kBlock), 0, stream, ws.recs, n, ws.cams, ws.culls, nv, eta, zn,
+                       d_scores);
 }
 
 }  // namespace
@@ -159,22 +416,19 @@ hipError_t launch_score(const float* planes, int64_t stride, int64_t n, const fl
 {
     const int nv = (prm.n_sub_views > 0 && prm.n_sub_views < n_views) ? prm.n_sub_views : n_views;
     hipLaunchKernelGGL(camera_prep, dim3((nv + kBlock - 1) / kBlock), dim3(kBlock), 0, stream, d_cams, n_views, nv,
-                       (float)prm.clamp_k, ws.cams);
+                       (float)prm.clamp_k, ws.cams, ws.culls);
     if (n == 0) return hipGetLastError();
-    const dim3 grid((unsigned)((n + kBlock - 1) / kBlock));
-    const int vis = prm.vis_mode == REFINE_VIS_ALPHA ? 1 : 0;
+    const bool binned = prm.score_path == REFINE_PATH_BINNED ||
+                        (prm.score_path == REFINE_PATH_AUTO && n >= kBinnedMinPrims);
     switch (prm.proj_mode) {
     case REFINE_PROJ_COV:
-        hipLaunchKernelGGL(score_views<REFINE_PROJ_COV>, grid, dim3(kBlock), 0, stream, planes, stride, (int)n,
-                           ws.cams, nv, d_stats, (float)prm.eta, (float)prm.z_near, vis, d_scores);
+        launch_mode<REFINE_PROJ_COV>(planes, stride, (int)n, prm, d_stats, d_scores, ws, nv, binned, stream);
         break;
     case REFINE_PROJ_DEPTH:
-        hipLaunchKernelGGL(score_views<REFINE_PROJ_DEPTH>, grid, dim3(kBlock), 0, stream, planes, stride, (int)n,
-                           ws.cams, nv, d_stats, (float)prm.eta, (float)prm.z_near, vis, d_scores);
+        launch_mode<REFINE_PROJ_DEPTH>(planes, stride, (int)n, prm, d_stats, d_scores, ws, nv, binned, stream);
         break;
     default:
-        hipLaunchKernelGGL(score_views<REFINE_PROJ_NONE>, grid, dim3(kBlock), 0, stream, planes, stride, (int)n,
-                           ws.cams, nv, d_stats, (float)prm.eta, (float)prm.z_near, vis, d_scores);
+        launch_mode<REFINE_PROJ_NONE>(planes, stride, (int)n, prm, d_stats, d_scores, ws, nv, binned, stream);
         break;
     }
     return hipGetLastError();

@@ -10,6 +10,10 @@
 // order and derives the features and lambda in FP64.  No floating-point
 // atomics: the result is bit-identical run to run.
 //
+// The same pass records the axis-aligned box of the finite centres (min/max
+// are order independent, so this is deterministic too); refine_score's
+// spatial binning quantises centres inside it.
+//
 // HBM traffic: 14 planes x 4 B = 56 B per primitive read (the 28 B of the
 // feature planes plus the non-finite check of the rest), 64 B per tile
 // written.
@@ -30,6 +34,7 @@ __global__ __launch_bounds__(kBlock) void stats_partial(const float* __restrict_
     const int base = tile * kTile;
     double sY = 0.0, sY2 = 0.0, sOpa = 0.0, sGem = 0.0;
     uint32_t bad = 0;
+    float bmin[3] = {INFINITY, INFINITY, INFINITY}, bmax[3] = {-INFINITY, -INFINITY, -INFINITY};
 #pragma unroll 4
     for (int k = 0; k < kItems; ++k) {
         const int i = base + k * kBlock + (int)threadIdx.x;
@@ -41,6 +46,12 @@ __global__ __launch_bounds__(kBlock) void stats_partial(const float* __restrict_
 #pragma unroll
         for (int p = 0; p < kScorePlanes; ++p) ok = ok && finite_bits(v[p]);
         bad += ok ? 0u : 1u;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            if (finite_bits(v[c])) {
+                bmin[c] = fminf(bmin[c], v[c]);
+                bmax[c] = fmaxf(bmax[c], v[c]);
+            }
         // luma of the DC colour (BT.601 weights)
         const float r = fmaf(kShC0, v[11], 0.5f);
         const float g = fmaf(kShC0, v[12], 0.5f);
@@ -64,7 +75,13 @@ __global__ __launch_bounds__(kBlock) void stats_partial(const float* __restrict_
     sOpa = wave_sum(sOpa);
     sGem = wave_sum(sGem);
     bad = wave_sum_u32(bad);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        bmin[k] = wave_min(bmin[k]);
+        bmax[k] = wave_max(bmax[k]);
+    }
     __shared__ double red[kWaves][5];
+    __shared__ float box[kWaves][6];
     const int wave = threadIdx.x / 64;
     if ((threadIdx.x & 63) == 0) {
         red[wave][0] = sY;
@@ -72,12 +89,27 @@ __global__ __launch_bounds__(kBlock) void stats_partial(const float* __restrict_
         red[wave][2] = sOpa;
         red[wave][3] = sGem;
         red[wave][4] = (double)bad;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            box[wave][k] = bmin[k];
+            box[wave][3 + k] = bmax[k];
+        }
     }
     __syncthreads();
     if (threadIdx.x < 5) {
         double acc = 0.0;
         for (int w = 0; w < kWaves; ++w) acc += red[w][threadIdx.x];
         part[(int64_t)tile * kStatSlots + threadIdx.x] = acc;
+    } else if (threadIdx.x < 8) {
+        // slots 5..7 carry the tile's box as bit patterns: min in the low and max in the high 32 bits
+        const int k = threadIdx.x - 5;
+        float lo = box[0][k], hi = box[0][3 + k];
+        for (int w = 1; w < kWaves; ++w) {
+            lo = fminf(lo, box[w][k]);
+            hi = fmaxf(hi, box[w][3 + k]);
+        }
+        const uint64_t bits = (uint64_t)__float_as_uint(lo) | ((uint64_t)__float_as_uint(hi) << 32);
+        part[(int64_t)tile * kStatSlots + threadIdx.x] = __longlong_as_double((long long)bits);
     }
 }
 
@@ -85,9 +117,28 @@ __global__ __launch_bounds__(kBlock) void stats_finalize(const double* __restric
                                                            refine_params prm, refine_stats_t* __restrict__ out)
 {
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int t = threadIdx.x; t < ntiles; t += kBlock)
+    float bmin[3] = {INFINITY, INFINITY, INFINITY}, bmax[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int t = threadIdx.x; t < ntiles; t += kBlock) {
 #pragma unroll
         for (int s = 0; s < 5; ++s) acc[s] += part[(int64_t)t * kStatSlots + s];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const uint64_t bits = (uint64_t)__double_as_longlong(part[(int64_t)t * kStatSlots + 5 + k]);
+            bmin[k] = fminf(bmin[k], __uint_as_float((uint32_t)bits));
+            bmax[k] = fmaxf(bmax[k], __uint_as_float((uint32_t)(bits >> 32)));
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        bmin[k] = wave_min(bmin[k]);
+        bmax[k] = wave_max(bmax[k]);
+    }
+    __shared__ float box[kWaves][6];
+    if ((threadIdx.x & 63) == 0)
+        for (int k = 0; k < 3; ++k) {
+            box[threadIdx.x / 64][k] = bmin[k];
+            box[threadIdx.x / 64][3 + k] = bmax[k];
+        }
     __shared__ double red[kWaves][5];
 #pragma unroll
     for (int s = 0; s < 5; ++s) acc[s] = wave_sum(acc[s]);
@@ -102,6 +153,16 @@ __global__ __launch_bounds__(kBlock) void stats_finalize(const double* __restric
         for (int w = 0; w < kWaves; ++w) tot[s] += red[w][s];
     }
     refine_stats_t r;
+    for (int k = 0; k < 3; ++k) {
+        float lo = box[0][k], hi = box[0][3 + k];
+        for (int w = 1; w < kWaves; ++w) {
+            lo = fminf(lo, box[w][k]);
+            hi = fmaxf(hi, box[w][3 + k]);
+        }
+        // no finite centre: an empty box at the origin
+        r.bbox_min[k] = lo <= hi ? lo : 0.0f;
+        r.bbox_max[k] = lo <= hi ? hi : 0.0f;
+    }
     r.n = n;
     r.n_nonfinite = (int64_t)tot[4];
     if (n > 0) {

@@ -17,7 +17,7 @@ def log(msg: str) -> None:
 
 def gpu_params(**kw):
     from paper_2606_09074_amd import _lib
-    p = _lib.Params(ETA, Z_NEAR, CLAMP_K, E_COL, E_OPA, E_LNGEM, 0, 0, 0, 0)
+    p = _lib.Params(ETA, Z_NEAR, CLAMP_K, E_COL, E_OPA, E_LNGEM, 0, 0, 0, 0, 0, 0)
     for k, v in kw.items():
         setattr(p, k, v)
     return p

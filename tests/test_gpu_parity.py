@@ -244,6 +244,9 @@ def test_medium_workload_full_parity(ratio):
     import oracle
     n_prune = oracle.n_prune(spec.n, ratio)
     r = run_gpu(planes, cams, ratio=ratio)
+    if ratio == 0.5:
+        d = run_gpu(planes, cams, params=gpu_params(score_path=1))
+        np.testing.assert_array_equal(r["scores"].view(np.uint32), d["scores"].view(np.uint32))
     check_stats(r["stats"], F, lam, "medium")
     check_scores(r["scores"], D, lo, hi, "medium scores")
     np.testing.assert_array_equal(r["keep"], expected_keep_from_scores(r["scores"], n_prune))
@@ -272,3 +275,53 @@ def test_large_workload_sampled_parity():
     check_scores(r["scores"][idx], D, lo, hi, "large sampled scores")
     np.testing.assert_array_equal(r["keep"], expected_keep_from_scores(r["scores"], n_prune))
     _check_compact(planes, spec.n, r)
+
+
+def _paths(planes, cams, n=None, **kw):
+    direct = run_gpu(planes, cams, n=n, params=gpu_params(score_path=1, **kw))
+    binned = run_gpu(planes, cams, n=n, params=gpu_params(score_path=2, **kw))
+    return direct, binned
+
+
+@pytest.mark.parametrize("name,n,mode", [("small", None, {}), ("small", 9000, {}), ("small", 777, {}),
+                                         ("small", None, dict(proj_mode=1)), ("small", None, dict(proj_mode=2)),
+                                         ("small", None, dict(vis_mode=1, n_sub_views=6)),
+                                         ("medium", 400_000, {})])
+def test_binned_and_direct_paths_bit_identical(name, n, mode):
+    """Culling skips only (group, view) pairs whose every primitive is gated
+    out, so the binned path must reproduce the direct path bit for bit."""
+    planes, cams, spec = workload(name)
+    sub = np.ascontiguousarray(planes[:, :n]) if n else planes
+    d, b = _paths(sub, cams, **mode)
+    np.testing.assert_array_equal(b["scores"].view(np.uint32), d["scores"].view(np.uint32))
+    log(f"[paths {name} n={sub.shape[1]} {mode}] identical; nonzero {int((d['scores'] > 0).sum())}")
+
+
+def test_binned_path_with_degenerate_and_nonfinite_inputs():
+    planes, cams, _ = workload("small")
+    sub = np.ascontiguousarray(planes[:, :20000])
+    sub[:, 100:164] = sub[:, 100:101]          # 64 identical primitives
+    sub[3:6, 200] = -30.0                      # vanishing scales
+    sub[3, 201] = 4.0                          # a huge one
+    sub[0, 300] = np.nan
+    sub[1, 301] = np.inf
+    sub[2, 302] = -np.inf
+    sub[6:10, 400] = 0.0                       # zero quaternion
+    d, b = _paths(sub, cams)
+    fin = np.isfinite(d["scores"])
+    np.testing.assert_array_equal(np.isfinite(b["scores"]), fin)
+    np.testing.assert_array_equal(b["scores"][fin].view(np.uint32), d["scores"][fin].view(np.uint32))
+    assert d["stats"]["n_nonfinite"] == 3
+
+
+def test_stats_bounding_box():
+    planes, cams, _ = workload("small")
+    sub = np.ascontiguousarray(planes[:, :10000])
+    sub[0, 7] = np.inf
+    sub[1, 8] = np.nan
+    r = run_gpu(sub, cams)
+    mu = sub[0:3].astype(np.float64)
+    for a in range(3):
+        v = mu[a][np.isfinite(mu[a])]
+        assert r["stats"]["bbox_min"][a] == np.float32(v.min())
+        assert r["stats"]["bbox_max"][a] == np.float32(v.max())
