@@ -190,6 +190,30 @@ refine_status refine_score(const refine_scene* scene, const float* d_cams, int32
                            float* d_scores, void* d_ws, size_t ws_bytes, void* stream);
 
 /*
+ * refine_score in two phases (refine_score = prepare, then views):
+ *  refine_score_prepare  builds the per-view constant tables and, on the
+ *                        binned path, the spatially binned, activated copy of
+ *                        the scene in the workspace.  It depends only on the
+ *                        scene, the cameras, the parameters and d_stats.
+ *  refine_score_views    evaluates every (primitive, view) pair that can
+ *                        contribute and writes d_scores.  It reads the tables
+ *                        the last refine_score_prepare on the same workspace
+ *                        built, so the same scene, n_views, params and d_stats
+ *                        must be passed (scene->planes is read only on the
+ *                        direct path).  Several views calls may follow one
+ *                        prepare (e.g. the same scene scored repeatedly).
+ *  d_evaluated (nullable, device int64) receives the number of pairs the
+ *  view loop evaluated in full (n * |V| on the direct path; on the binned
+ *  path, pairs of 64-primitive groups whose bound reaches the view).
+ */
+refine_status refine_score_prepare(const refine_scene* scene, const float* d_cams, int32_t n_views,
+                                   const refine_params* params, const refine_stats_t* d_stats,
+                                   void* d_ws, size_t ws_bytes, void* stream);
+refine_status refine_score_views(const refine_scene* scene, int32_t n_views, const refine_params* params,
+                                 const refine_stats_t* d_stats, float* d_scores, int64_t* d_evaluated,
+                                 void* d_ws, size_t ws_bytes, void* stream);
+
+/*
  * Global ranking and ratio selection (Sec. 3.3): primitives are ordered by
  * (score, index) and the first n_prune are removed, n_prune =
  * refine_prune_count(n, ratio), or n_prune_override when it is >= 0 (then

@@ -24,7 +24,8 @@ VIS_ALPHA, VIS_NONE = 0, 1
 PATH_AUTO, PATH_DIRECT, PATH_BINNED = 0, 1, 2
 
 EXPORTED = ("refine_version", "refine_status_string", "refine_params_default", "refine_prune_count",
-            "refine_workspace_size", "refine_stats", "refine_score", "refine_select", "refine_compact")
+            "refine_workspace_size", "refine_stats", "refine_score", "refine_score_prepare", "refine_score_views",
+            "refine_select", "refine_compact")
 
 
 class Scene(ctypes.Structure):
@@ -83,6 +84,10 @@ def load():
     lib.refine_stats.restype = i32
     lib.refine_score.argtypes = [ctypes.POINTER(Scene), P, i32, ctypes.POINTER(Params), P, P, P, sz, P]
     lib.refine_score.restype = i32
+    lib.refine_score_prepare.argtypes = [ctypes.POINTER(Scene), P, i32, ctypes.POINTER(Params), P, P, sz, P]
+    lib.refine_score_prepare.restype = i32
+    lib.refine_score_views.argtypes = [ctypes.POINTER(Scene), i32, ctypes.POINTER(Params), P, P, P, P, sz, P]
+    lib.refine_score_views.restype = i32
     lib.refine_select.argtypes = [P, i64, ctypes.c_double, i64, P, P, P, P, sz, P]
     lib.refine_select.restype = i32
     lib.refine_compact.argtypes = [ctypes.POINTER(Scene), P, ctypes.POINTER(Scene), P, P, P, sz, P]

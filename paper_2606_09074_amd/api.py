@@ -15,7 +15,8 @@ from . import _lib
 from ._lib import Params, Scene, Stats, check, default_params
 
 __all__ = ["Params", "default_params", "workspace", "workspace_size", "prune_count", "refine_stats",
-           "refine_score", "refine_select", "refine_compact", "stats_from_tensor", "prune", "version"]
+           "refine_score", "refine_score_prepare", "refine_score_views", "refine_select", "refine_compact",
+           "stats_from_tensor", "prune", "version"]
 
 
 def version() -> str:
@@ -87,6 +88,38 @@ def refine_score(planes: torch.Tensor, cams: torch.Tensor, stats: torch.Tensor, 
     check(_lib.load().refine_score(ctypes.byref(sc), _ptr(cams), cams.shape[0], ctypes.byref(params),
                                    _ptr(stats), _ptr(scores_out), _ptr(ws), ws.numel(), _stream_ptr(stream)),
           "refine_score")
+
+
+def _check_cams(cams: torch.Tensor) -> None:
+    if cams.dim() != 2 or cams.shape[1] != 18 or cams.dtype != torch.float32 or not cams.is_cuda \
+            or not cams.is_contiguous():
+        raise ValueError("cams must be a contiguous float32 [V, 18] GPU tensor")
+
+
+def refine_score_prepare(planes: torch.Tensor, cams: torch.Tensor, stats: torch.Tensor, ws: torch.Tensor,
+                         params: Optional[Params] = None, n: Optional[int] = None, stream=None) -> None:
+    """First phase of refine_score: view tables and (binned path) the binned scene copy in ``ws``."""
+    params = params or default_params()
+    sc = _scene(planes, n)
+    _check_cams(cams)
+    check(_lib.load().refine_score_prepare(ctypes.byref(sc), _ptr(cams), cams.shape[0], ctypes.byref(params),
+                                           _ptr(stats), _ptr(ws), ws.numel(), _stream_ptr(stream)),
+          "refine_score_prepare")
+
+
+def refine_score_views(planes: torch.Tensor, n_views: int, stats: torch.Tensor, scores_out: torch.Tensor,
+                       ws: torch.Tensor, params: Optional[Params] = None, evaluated_out: Optional[torch.Tensor] = None,
+                       n: Optional[int] = None, stream=None) -> None:
+    """Second phase of refine_score: the view loop over the prepared workspace."""
+    params = params or default_params()
+    sc = _scene(planes, n)
+    if scores_out.dtype != torch.float32 or scores_out.numel() < sc.n or not scores_out.is_cuda:
+        raise ValueError("scores_out must be a float32 GPU tensor of at least n elements")
+    if evaluated_out is not None and (evaluated_out.dtype != torch.int64 or not evaluated_out.is_cuda):
+        raise ValueError("evaluated_out must be an int64 GPU tensor")
+    check(_lib.load().refine_score_views(ctypes.byref(sc), int(n_views), ctypes.byref(params), _ptr(stats),
+                                         _ptr(scores_out), _ptr(evaluated_out), _ptr(ws), ws.numel(),
+                                         _stream_ptr(stream)), "refine_score_views")
 
 
 def refine_select(scores: torch.Tensor, keep_out: torch.Tensor, ws: torch.Tensor, ratio: float = 0.5,

@@ -71,6 +71,7 @@ size_t workspace_layout(int64_t n, int32_t n_views, bool score, void* base, Work
     const size_t o_cnt = off;   off += align_up(sizeof(uint32_t) * nt);
     const size_t o_toff = off;  off += align_up(sizeof(uint32_t) * nt);
     // sections only refine_score uses come last, so the other calls need a prefix only
+    const size_t o_eval = off;  off += score ? align_up(sizeof(unsigned long long)) : 0;
     const size_t o_cams = off;  off += score ? align_up(sizeof(CamRec) * nv) : 0;
     const size_t o_cull = off;  off += score ? align_up(sizeof(CullRec) * nv) : 0;
     const size_t o_ccnt = off;  off += score ? align_up(sizeof(uint32_t) * kCells) : 0;
@@ -90,6 +91,7 @@ size_t workspace_layout(int64_t n, int32_t n_views, bool score, void* base, Work
         ws->cell_cur = score ? reinterpret_cast<uint32_t*>(b + o_ccur) : nullptr;
         ws->dest = score ? reinterpret_cast<uint32_t*>(b + o_dest) : nullptr;
         ws->recs = score ? reinterpret_cast<PrimRec*>(b + o_recs) : nullptr;
+        ws->evaluated = score ? reinterpret_cast<unsigned long long*>(b + o_eval) : nullptr;
     }
     return off;
 }
@@ -161,21 +163,60 @@ refine_status refine_stats(const refine_scene* scene, const refine_params* param
     return e == hipSuccess ? REFINE_OK : REFINE_E_HIP;
 }
 
-refine_status refine_score(const refine_scene* scene, const float* d_cams, int32_t n_views,
-                           const refine_params* params, const refine_stats_t* d_stats, float* d_scores,
-                           void* d_ws, size_t ws_bytes, void* stream)
+namespace {
+
+refine_status check_score_args(const refine_scene* scene, int32_t n_views, const refine_params* params,
+                               const refine_stats_t* d_stats)
 {
     refine_status s = check_scene(scene, false);
     if (s != REFINE_OK) return s;
     if ((s = check_params(params)) != REFINE_OK) return s;
-    if (n_views < 1 || !d_cams || !d_stats) return REFINE_E_INVALID;
+    if (n_views < 1 || !d_stats) return REFINE_E_INVALID;
     if (n_views > kMaxViews) return REFINE_E_UNSUPPORTED;
+    return REFINE_OK;
+}
+
+}  // namespace
+
+refine_status refine_score_prepare(const refine_scene* scene, const float* d_cams, int32_t n_views,
+                                   const refine_params* params, const refine_stats_t* d_stats, void* d_ws,
+                                   size_t ws_bytes, void* stream)
+{
+    refine_status s = check_score_args(scene, n_views, params, d_stats);
+    if (s != REFINE_OK) return s;
+    if (!d_cams) return REFINE_E_INVALID;
+    Workspace ws;
+    if ((s = check_workspace(scene->n, n_views, true, d_ws, ws_bytes, &ws)) != REFINE_OK) return s;
+    const hipError_t e = launch_score_prepare(static_cast<const float*>(scene->planes), scene->stride, scene->n,
+                                              d_cams, n_views, *params, d_stats, ws, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? REFINE_OK : REFINE_E_HIP;
+}
+
+refine_status refine_score_views(const refine_scene* scene, int32_t n_views, const refine_params* params,
+                                 const refine_stats_t* d_stats, float* d_scores, int64_t* d_evaluated, void* d_ws,
+                                 size_t ws_bytes, void* stream)
+{
+    refine_status s = check_score_args(scene, n_views, params, d_stats);
+    if (s != REFINE_OK) return s;
     if (scene->n > 0 && !d_scores) return REFINE_E_INVALID;
     Workspace ws;
     if ((s = check_workspace(scene->n, n_views, true, d_ws, ws_bytes, &ws)) != REFINE_OK) return s;
-    const hipError_t e = launch_score(static_cast<const float*>(scene->planes), scene->stride, scene->n, d_cams,
-                                      n_views, *params, d_stats, d_scores, ws, static_cast<hipStream_t>(stream));
+    const hipError_t e = launch_score_views(static_cast<const float*>(scene->planes), scene->stride, scene->n, n_views,
+                                            *params, d_stats, d_scores, d_evaluated, ws,
+                                            static_cast<hipStream_t>(stream));
     return e == hipSuccess ? REFINE_OK : REFINE_E_HIP;
+}
+
+refine_status refine_score(const refine_scene* scene, const float* d_cams, int32_t n_views,
+                           const refine_params* params, const refine_stats_t* d_stats, float* d_scores,
+                           void* d_ws, size_t ws_bytes, void* stream)
+{
+    refine_status s = check_score_args(scene, n_views, params, d_stats);
+    if (s != REFINE_OK) return s;
+    if (!d_cams || (scene->n > 0 && !d_scores)) return REFINE_E_INVALID;
+    s = refine_score_prepare(scene, d_cams, n_views, params, d_stats, d_ws, ws_bytes, stream);
+    if (s != REFINE_OK) return s;
+    return refine_score_views(scene, n_views, params, d_stats, d_scores, nullptr, d_ws, ws_bytes, stream);
 }
 
 refine_status refine_select(const float* d_scores, int64_t n, double ratio, int64_t n_prune_override,

@@ -95,6 +95,115 @@ __global__ __launch_bounds__(kBlock) void compact_scatter(const float* __restric
     }
 }
 
+// compact_scatter for 16-byte aligned planes (stride a multiple of 4) and a
+// 4-byte aligned mask.  A tile is 4 rows of 1024 primitives; each lane loads
+// 4 consecutive primitives of a row with one 16-byte load per plane.  The
+// survivors of two planes are packed in LDS at their tile-local positions
+// (per-row exclusive scans in index order: the copy stays stable), then
+// written out with contiguous, fully active 4-byte stores.
+constexpr int kVecRows = kTile / (4 * kBlock);   // 4
+constexpr int kStagePlanes = 2;
+
+__global__ __launch_bounds__(kBlock) void compact_scatter_lds(const float* __restrict__ in, int64_t in_stride, int n,
+                                                                const uint8_t* __restrict__ keep,
+                                                                const uint32_t* __restrict__ tile_off,
+                                                                const uint32_t* __restrict__ tile_cnt,
+                                                                float* __restrict__ out, int64_t out_stride,
+                                                                int64_t capacity, int32_t* __restrict__ index_map)
+{
+    __shared__ uint32_t wtot[kVecRows][kWaves];
+    __shared__ float stage[kStagePlanes][kTile];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int base = blockIdx.x * kTile;
+    uint32_t flags[kVecRows], incl[kVecRows];
+#pragma unroll
+    for (int r = 0; r < kVecRows; ++r) {
+        const int i0 = base + r * 4 * kBlock + 4 * (int)threadIdx.x;
+        uint32_t f = 0u;
+        if (i0 + 3 < n) {
+            const uint32_t w = *reinterpret_cast<const uint32_t*>(keep + i0);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) f |= ((w >> (8 * j)) & 0xFFu) ? (1u << j) : 0u;
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) f |= (i0 + j < n && keep[i0 + j]) ? (1u << j) : 0u;
+        }
+        flags[r] = f;
+        uint32_t c = (uint32_t)__popc(f);
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(c, o, 64);
+            if (lane >= o) c += y;
+        }
+        incl[r] = c;
+        if (lane == 63) wtot[r][wave] = c;
+    }
+    __syncthreads();
+    // tile-local position of this lane's first survivor in each row
+    uint32_t lstart[kVecRows];
+    uint32_t row = 0;
+#pragma unroll
+    for (int r = 0; r < kVecRows; ++r) {
+        uint32_t before = 0, tot = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) {
+            if (w < wave) before += wtot[r][w];
+            tot += wtot[r][w];
+        }
+        lstart[r] = row + before + incl[r] - (uint32_t)__popc(flags[r]);
+        row += tot;
+    }
+    const int64_t out0 = (int64_t)tile_off[blockIdx.x];
+    const int64_t room = capacity - out0;
+    const int kept = (int)min((int64_t)tile_cnt[blockIdx.x], room > 0 ? room : (int64_t)0);
+    if (index_map) {
+#pragma unroll
+        for (int r = 0; r < kVecRows; ++r) {
+            const int i0 = base + r * 4 * kBlock + 4 * (int)threadIdx.x;
+            uint32_t k = 0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if ((flags[r] >> j) & 1u) {
+                    if ((int)(lstart[r] + k) < kept) index_map[out0 + lstart[r] + k] = i0 + j;
+                    ++k;
+                }
+        }
+    }
+    if (kept == 0) return;   // uniform across the block
+    for (int p0 = 0; p0 < kPlanes; p0 += kStagePlanes) {
+#pragma unroll
+        for (int q = 0; q < kStagePlanes; ++q) {
+            if (p0 + q >= kPlanes) break;
+            const float* src = in + (int64_t)(p0 + q) * in_stride;
+#pragma unroll
+            for (int r = 0; r < kVecRows; ++r) {
+                if (!flags[r]) continue;
+                const int i0 = base + r * 4 * kBlock + 4 * (int)threadIdx.x;
+                float v[4];
+                if (i0 + 3 < n) {
+                    const float4 x = *reinterpret_cast<const float4*>(src + i0);
+                    v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+                } else {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) v[j] = (i0 + j < n) ? src[i0 + j] : 0.0f;
+                }
+                uint32_t k = 0;
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if ((flags[r] >> j) & 1u) stage[q][lstart[r] + k++] = v[j];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kStagePlanes; ++q) {
+            if (p0 + q >= kPlanes) break;
+            float* dst = out + (int64_t)(p0 + q) * out_stride + out0;
+            for (int j = threadIdx.x; j < kept; j += kBlock) dst[j] = stage[q][j];
+        }
+        __syncthreads();
+    }
+}
+
 }  // namespace
 
 hipError_t launch_compact(const float* in, int64_t in_stride, int64_t n, const uint8_t* d_keep, float* out,
@@ -106,7 +215,12 @@ hipError_t launch_compact(const float* in, int64_t in_stride, int64_t n, const u
         hipLaunchKernelGGL(compact_count, dim3(ntiles), dim3(kBlock), 0, stream, d_keep, (int)n, ws.tile_cnt);
     hipLaunchKernelGGL(compact_scan, dim3(1), dim3(kScanThreads), 0, stream, ws.tile_cnt, ws.tile_off, ntiles,
                        d_n_out);
-    if (ntiles > 0)
+    const bool vec = (reinterpret_cast<uintptr_t>(in) % 16 == 0) && (in_stride % 4 == 0) &&
+                     (reinterpret_cast<uintptr_t>(d_keep) % 4 == 0);
+    if (ntiles > 0 && vec)
+        hipLaunchKernelGGL(compact_scatter_lds, dim3(ntiles), dim3(kBlock), 0, stream, in, in_stride, (int)n, d_keep,
+                           ws.tile_off, ws.tile_cnt, out, out_stride, capacity, d_index_map);
+    else if (ntiles > 0)
         hipLaunchKernelGGL(compact_scatter, dim3(ntiles), dim3(kBlock), 0, stream, in, in_stride, (int)n, d_keep,
                            ws.tile_off, out, out_stride, capacity, d_index_map);
     return hipGetLastError();

@@ -74,7 +74,7 @@ struct PrimRec {
 static_assert(sizeof(PrimRec) == 64, "primitive record size");
 
 constexpr int kCellBits = 4;                       // per axis
-constexpr int kCells = 1 << (3 * kCellBits);       // 4096 Morton cells
+constexpr int kCells = 1 << (3 * kCellBits);       // 4096 Morton cells (16 KB of LDS counters)
 
 struct Workspace {
     SelectState* sel;
@@ -89,6 +89,7 @@ struct Workspace {
     uint32_t* cell_cur;      // [kCells]
     uint32_t* dest;          // [n] binned position of each primitive
     PrimRec* recs;           // [n]
+    unsigned long long* evaluated;   // pairs evaluated by the last view loop
 };
 
 inline int64_t num_tiles(int64_t n) { return (n + kTile - 1) / kTile; }
@@ -100,9 +101,12 @@ size_t workspace_layout(int64_t n, int32_t n_views, bool score, void* base, Work
 // Launchers (validated arguments; return the hipGetLastError of the launch).
 hipError_t launch_stats(const float* planes, int64_t stride, int64_t n, const refine_params& prm,
                         refine_stats_t* d_stats, const Workspace& ws, hipStream_t stream);
-hipError_t launch_score(const float* planes, int64_t stride, int64_t n, const float* d_cams,
-                        int32_t n_views, const refine_params& prm, const refine_stats_t* d_stats,
-                        float* d_scores, const Workspace& ws, hipStream_t stream);
+hipError_t launch_score_prepare(const float* planes, int64_t stride, int64_t n, const float* d_cams,
+                                int32_t n_views, const refine_params& prm, const refine_stats_t* d_stats,
+                                const Workspace& ws, hipStream_t stream);
+hipError_t launch_score_views(const float* planes, int64_t stride, int64_t n, int32_t n_views,
+                              const refine_params& prm, const refine_stats_t* d_stats, float* d_scores,
+                              int64_t* d_evaluated, const Workspace& ws, hipStream_t stream);
 hipError_t launch_select(const float* d_scores, int64_t n, int64_t n_prune, uint8_t* d_keep,
                          int64_t* d_n_keep, uint32_t* d_threshold, const Workspace& ws,
                          hipStream_t stream);

@@ -32,7 +32,8 @@
 // by the Morton code of a 16^3 grid over the centres' bounding box (per-tile
 // LDS histograms, so a crowded cell costs one global atomic per tile, not
 // per primitive) and write each activated primitive as a 64-byte record in
-// cell order.  score_binned
+// cell order.  (A 32^3 grid culls ~10% more pairs but its extra global
+// atomics cost about as much as they save.)  score_binned
 // then gives each wave 64 spatially close primitives: the wave bounds them by
 // a sphere (centre c, radius R) and by their largest scale s_max; each lane
 // tests one view against the sphere, and the ballot of the results is the
@@ -50,6 +51,10 @@ namespace {
 constexpr float kShC0 = 0.28209479177387814f;
 constexpr float kCullMargin = 1.01f;
 constexpr int64_t kBinnedMinPrims = 65536;
+#ifndef REFINE_BINNED_PPL
+#define REFINE_BINNED_PPL 1
+#endif
+constexpr int kBinnedPPL = REFINE_BINNED_PPL;   // binned records per lane
 
 __global__ __launch_bounds__(kBlock) void camera_prep(const float* __restrict__ cams, int n_views, int nv,
                                                         float clamp_k, CamRec* __restrict__ out,
@@ -251,7 +256,14 @@ __global__ __launch_bounds__(kBlock) void bin_zero(uint32_t* __restrict__ cnt)
     if (c < kCells) cnt[c] = 0u;
 }
 
-// Cell histogram: per tile in LDS, then one global add per (tile, cell).
+// Binning tiles are the 4096-primitive tiles of the other kernels.  Each
+// tile counts its cells in LDS and touches the global cell arrays once per
+// occupied cell, in cell order (consecutive lanes hit consecutive counters,
+// so the atomics coalesce); global atomics are memory transactions here, so
+// their number, not the LDS work, sets the cost.
+constexpr int kCellsPerThread = kCells / kBlock;   // 16
+
+// Cell histogram of the tile's primitives.
 __global__ __launch_bounds__(kBlock) void bin_hist(const float* __restrict__ planes, int64_t stride, int n,
                                                      const refine_stats_t* __restrict__ st,
                                                      uint32_t* __restrict__ cnt)
@@ -266,8 +278,11 @@ __global__ __launch_bounds__(kBlock) void bin_hist(const float* __restrict__ pla
         if (i < n) atomicAdd(&h[cell_of(planes[i], planes[stride + i], planes[2 * stride + i], st)], 1u);
     }
     __syncthreads();
-    for (int c = threadIdx.x; c < kCells; c += kBlock)
+#pragma unroll
+    for (int j = 0; j < kCellsPerThread; ++j) {
+        const int c = j * kBlock + (int)threadIdx.x;
         if (h[c]) atomicAdd(&cnt[c], h[c]);
+    }
 }
 
 __global__ __launch_bounds__(kScanThreads) void bin_scan(const uint32_t* __restrict__ cnt, uint32_t* __restrict__ cur)
@@ -275,8 +290,8 @@ __global__ __launch_bounds__(kScanThreads) void bin_scan(const uint32_t* __restr
     block_exclusive_scan(cnt, cur, kCells);
 }
 
-// Counting-sort ranks: each tile reserves one output range per cell with a
-// single global atomic; its primitives take consecutive slots inside it.
+// Counting-sort ranks: each tile reserves one output range per occupied cell
+// with a single global atomic; its primitives take consecutive slots in it.
 __global__ __launch_bounds__(kBlock) void bin_rank(const float* __restrict__ planes, int64_t stride, int n,
                                                      const refine_stats_t* __restrict__ st, uint32_t* __restrict__ cur,
                                                      uint32_t* __restrict__ dest)
@@ -297,8 +312,16 @@ __global__ __launch_bounds__(kBlock) void bin_rank(const float* __restrict__ pla
         }
     }
     __syncthreads();
-    for (int c = threadIdx.x; c < kCells; c += kBlock)
-        if (h[c]) h[c] = atomicAdd(&cur[c], h[c]);
+    // all reservations of this thread are issued before any result is used
+    uint32_t got[kCellsPerThread];
+#pragma unroll
+    for (int j = 0; j < kCellsPerThread; ++j) {
+        const int c = j * kBlock + (int)threadIdx.x;
+        const uint32_t m = h[c];
+        got[j] = m ? atomicAdd(&cur[c], m) : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < kCellsPerThread; ++j) h[j * kBlock + (int)threadIdx.x] = got[j];
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
@@ -346,91 +369,174 @@ __device__ inline bool cull_pass(const CullRec& q, float cx, float cy, float cz,
     return ok;
 }
 
-template <int PROJ>
+// PPL binned records per lane: a wave owns a group of 64 PPL consecutive
+// records (lane l holds records l, l + 64, ...), bounds them by one sphere and
+// evaluates each visible view for all of them, so the per-view overhead
+// (record loads, loop control) is shared by PPL pairs.
+template <int PROJ, int PPL>
 __global__ __launch_bounds__(kBlock) void score_binned(const PrimRec* __restrict__ recs, int n,
                                                          const CamRec* __restrict__ cams,
                                                          const CullRec* __restrict__ culls, int nv, float eta,
-                                                         float z_near, float* __restrict__ out)
+                                                         float z_near, float* __restrict__ out,
+                                                         unsigned long long* __restrict__ evaluated)
 {
-    const int j = blockIdx.x * kBlock + threadIdx.x;
     const int lane = threadIdx.x & 63;
-    const PrimRec r = recs[min(j, n - 1)];   // lanes past the end repeat the last record
-    Prim p;
-    p.mx = r.mu[0]; p.my = r.mu[1]; p.mz = r.mu[2];
-    p.L00 = r.L[0]; p.L01 = r.L[1]; p.L02 = r.L[2];
-    p.L10 = r.L[3]; p.L11 = r.L[4]; p.L12 = r.L[5];
-    p.L20 = r.L[6]; p.L21 = r.L[7]; p.L22 = r.L[8];
-    p.S = 0.0f;
-    // bounding sphere of the wave's centres and its largest scale
-    const float cx = 0.5f * (wave_min(p.mx) + wave_max(p.mx));
-    const float cy = 0.5f * (wave_min(p.my) + wave_max(p.my));
-    const float cz = 0.5f * (wave_min(p.mz) + wave_max(p.mz));
-    const float dx = p.mx - cx, dy = p.my - cy, dz = p.mz - cz;
+    const int g0 = (blockIdx.x * kBlock + (int)threadIdx.x - lane) * PPL;   // first record of the wave's group
+    Prim p[PPL];
+    float pre[PPL];
+    int idx[PPL];
+    float smax = 0.0f;
+#pragma unroll
+    for (int k = 0; k < PPL; ++k) {
+        const int j = g0 + k * 64 + lane;
+        const PrimRec r = recs[min(j, n - 1)];   // lanes past the end repeat the last record
+        p[k].mx = r.mu[0]; p[k].my = r.mu[1]; p[k].mz = r.mu[2];
+        p[k].L00 = r.L[0]; p[k].L01 = r.L[1]; p[k].L02 = r.L[2];
+        p[k].L10 = r.L[3]; p[k].L11 = r.L[4]; p[k].L12 = r.L[5];
+        p[k].L20 = r.L[6]; p[k].L21 = r.L[7]; p[k].L22 = r.L[8];
+        p[k].S = 0.0f;
+        pre[k] = r.pre;
+        idx[k] = j < n ? r.idx : -1;
+        smax = fmaxf(smax, r.smax);
+    }
+    // bounding sphere of the group's centres and its largest scale
+    float lo[3] = {p[0].mx, p[0].my, p[0].mz}, hi[3] = {p[0].mx, p[0].my, p[0].mz};
+#pragma unroll
+    for (int k = 1; k < PPL; ++k) {
+        lo[0] = fminf(lo[0], p[k].mx); hi[0] = fmaxf(hi[0], p[k].mx);
+        lo[1] = fminf(lo[1], p[k].my); hi[1] = fmaxf(hi[1], p[k].my);
+        lo[2] = fminf(lo[2], p[k].mz); hi[2] = fmaxf(hi[2], p[k].mz);
+    }
+    const float cx = 0.5f * (wave_min(lo[0]) + wave_max(hi[0]));
+    const float cy = 0.5f * (wave_min(lo[1]) + wave_max(hi[1]));
+    const float cz = 0.5f * (wave_min(lo[2]) + wave_max(hi[2]));
+    float d2 = 0.0f;
+#pragma unroll
+    for (int k = 0; k < PPL; ++k) {
+        const float dx = p[k].mx - cx, dy = p[k].my - cy, dz = p[k].mz - cz;
+        d2 = fmaxf(d2, dx * dx + dy * dy + dz * dz);
+    }
     const float ca = fabsf(cx) + fabsf(cy) + fabsf(cz);
-    const float rm = sqrtf(wave_max(dx * dx + dy * dy + dz * dz)) * kCullMargin + 1e-4f * (ca + 1.0f);
-    const float sg = wave_max(r.smax);
-    // a non-finite bound (non-finite input) disables culling for this wave
+    const float rm = sqrtf(wave_max(d2)) * kCullMargin + 1e-4f * (ca + 1.0f);
+    const float sg = wave_max(smax);
+    // a non-finite bound (non-finite input) disables culling for this group
     const bool no_cull = !(rm < INFINITY) || !(sg < INFINITY) || !(ca < INFINITY);
+    uint32_t n_eval = 0;
     for (int v0 = 0; v0 < nv; v0 += 64) {
         const int v = v0 + lane;
         bool vis = false;
         if (v < nv) vis = no_cull || cull_pass(culls[v], cx, cy, cz, rm, sg, ca, z_near);
         uint64_t m = __ballot(vis);
+        n_eval += (uint32_t)__popcll(m);
         while (m) {
             const int b = __builtin_ctzll(m);
             m &= m - 1;
-            eval_pair<PROJ>(cams[v0 + b], p, eta, z_near);
+            const CamRec& c = cams[v0 + b];
+#pragma unroll
+            for (int k = 0; k < PPL; ++k) eval_pair<PROJ>(c, p[k], eta, z_near);
         }
     }
-    if (j < n) out[r.idx] = r.pre * p.S;
+#pragma unroll
+    for (int k = 0; k < PPL; ++k)
+        if (idx[k] >= 0) out[idx[k]] = pre[k] * p[k].S;
+    if (evaluated && lane == 0) {
+        const int valid = max(0, min(64 * PPL, n - g0));   // records of this group
+        atomicAdd(evaluated, (unsigned long long)n_eval * (unsigned long long)valid);
+    }
+}
+
+__global__ void counter_reset(unsigned long long* c) { *c = 0ull; }
+
+__global__ void counter_store(const unsigned long long* c, int64_t* out, int64_t direct_pairs)
+{
+    *out = direct_pairs >= 0 ? direct_pairs : (int64_t)*c;
 }
 
 template <int PROJ>
-void launch_mode(const float* planes, int64_t stride, int n, const refine_params& prm, const refine_stats_t* d_stats,
-                 float* d_scores, const Workspace& ws, int nv, bool binned, hipStream_t stream)
+void prepare_mode(const float* planes, int64_t stride, int n, const refine_params& prm, const refine_stats_t* d_stats,
+                  const Workspace& ws, int nv, hipStream_t stream)
 {
     const int vis = prm.vis_mode == REFINE_VIS_ALPHA ? 1 : 0;
-    const float eta = (float)prm.eta, zn = (float)prm.z_near;
     const dim3 grid((unsigned)((n + kBlock - 1) / kBlock));
-    if (!binned) {
-        hipLaunchKernelGGL((score_direct<PROJ>), grid, dim3(kBlock), 0, stream, planes, stride, n, ws.cams, nv, d_stats,
-                           eta, zn, vis, d_scores);
-        return;
-    }
     const dim3 tiles((unsigned)num_tiles(n));
-    hipLaunchKernelGGL(bin_zero, dim3(kCells / kBlock), dim3(kBlock), 0, stream, ws.cell_cnt);
+    hipLaunchKernelGGL(bin_zero, dim3((kCells + kBlock - 1) / kBlock), dim3(kBlock), 0, stream, ws.cell_cnt);
     hipLaunchKernelGGL(bin_hist, tiles, dim3(kBlock), 0, stream, planes, stride, n, d_stats, ws.cell_cnt);
     hipLaunchKernelGGL(bin_scan, dim3(1), dim3(kScanThreads), 0, stream, ws.cell_cnt, ws.cell_cur);
     hipLaunchKernelGGL(bin_rank, tiles, dim3(kBlock), 0, stream, planes, stride, n, d_stats, ws.cell_cur, ws.dest);
     hipLaunchKernelGGL((bin_scatter<PROJ>), grid, dim3(kBlock), 0, stream, planes, stride, n, d_stats, vis, nv, ws.dest,
                        ws.recs);
-    hipLaunchKernelGGL((score_binned<PROJ>), grid, dim3(kBlock), 0, stream, ws.recs, n, ws.cams, ws.culls, nv, eta, zn,
-                       d_scores);
+}
+
+template <int PROJ>
+void views_mode(const float* planes, int64_t stride, int n, const refine_params& prm, const refine_stats_t* d_stats,
+                float* d_scores, unsigned long long* evaluated, const Workspace& ws, int nv, bool binned,
+                hipStream_t stream)
+{
+    const int vis = prm.vis_mode == REFINE_VIS_ALPHA ? 1 : 0;
+    const float eta = (float)prm.eta, zn = (float)prm.z_near;
+    const dim3 grid((unsigned)((n + kBlock - 1) / kBlock));
+    if (binned)
+        hipLaunchKernelGGL((score_binned<PROJ, kBinnedPPL>), dim3((unsigned)((n + kBlock * kBinnedPPL - 1) /
+                                                                             (kBlock * kBinnedPPL))),
+                           dim3(kBlock), 0, stream, ws.recs, n, ws.cams, ws.culls, nv, eta, zn, d_scores, evaluated);
+    else
+        hipLaunchKernelGGL((score_direct<PROJ>), grid, dim3(kBlock), 0, stream, planes, stride, n, ws.cams, nv, d_stats,
+                           eta, zn, vis, d_scores);
+}
+
+int views_of(const refine_params& prm, int32_t n_views)
+{
+    return (prm.n_sub_views > 0 && prm.n_sub_views < n_views) ? prm.n_sub_views : n_views;
+}
+
+bool binned_path(const refine_params& prm, int64_t n)
+{
+    return prm.score_path == REFINE_PATH_BINNED || (prm.score_path == REFINE_PATH_AUTO && n >= kBinnedMinPrims);
 }
 
 }  // namespace
 
-hipError_t launch_score(const float* planes, int64_t stride, int64_t n, const float* d_cams, int32_t n_views,
-                        const refine_params& prm, const refine_stats_t* d_stats, float* d_scores,
-                        const Workspace& ws, hipStream_t stream)
+hipError_t launch_score_prepare(const float* planes, int64_t stride, int64_t n, const float* d_cams, int32_t n_views,
+                                const refine_params& prm, const refine_stats_t* d_stats, const Workspace& ws,
+                                hipStream_t stream)
 {
-    const int nv = (prm.n_sub_views > 0 && prm.n_sub_views < n_views) ? prm.n_sub_views : n_views;
+    const int nv = views_of(prm, n_views);
     hipLaunchKernelGGL(camera_prep, dim3((nv + kBlock - 1) / kBlock), dim3(kBlock), 0, stream, d_cams, n_views, nv,
                        (float)prm.clamp_k, ws.cams, ws.culls);
-    if (n == 0) return hipGetLastError();
-    const bool binned = prm.score_path == REFINE_PATH_BINNED ||
-                        (prm.score_path == REFINE_PATH_AUTO && n >= kBinnedMinPrims);
+    if (n == 0 || !binned_path(prm, n)) return hipGetLastError();
     switch (prm.proj_mode) {
-    case REFINE_PROJ_COV:
-        launch_mode<REFINE_PROJ_COV>(planes, stride, (int)n, prm, d_stats, d_scores, ws, nv, binned, stream);
-        break;
-    case REFINE_PROJ_DEPTH:
-        launch_mode<REFINE_PROJ_DEPTH>(planes, stride, (int)n, prm, d_stats, d_scores, ws, nv, binned, stream);
-        break;
-    default:
-        launch_mode<REFINE_PROJ_NONE>(planes, stride, (int)n, prm, d_stats, d_scores, ws, nv, binned, stream);
-        break;
+    case REFINE_PROJ_COV: prepare_mode<REFINE_PROJ_COV>(planes, stride, (int)n, prm, d_stats, ws, nv, stream); break;
+    case REFINE_PROJ_DEPTH: prepare_mode<REFINE_PROJ_DEPTH>(planes, stride, (int)n, prm, d_stats, ws, nv, stream); break;
+    default: prepare_mode<REFINE_PROJ_NONE>(planes, stride, (int)n, prm, d_stats, ws, nv, stream); break;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_score_views(const float* planes, int64_t stride, int64_t n, int32_t n_views,
+                              const refine_params& prm, const refine_stats_t* d_stats, float* d_scores,
+                              int64_t* d_evaluated, const Workspace& ws, hipStream_t stream)
+{
+    const int nv = views_of(prm, n_views);
+    const bool binned = binned_path(prm, n);
+    unsigned long long* counter = (d_evaluated && binned) ? ws.evaluated : nullptr;
+    if (counter) hipLaunchKernelGGL(counter_reset, dim3(1), dim3(1), 0, stream, counter);
+    if (n > 0) {
+        switch (prm.proj_mode) {
+        case REFINE_PROJ_COV:
+            views_mode<REFINE_PROJ_COV>(planes, stride, (int)n, prm, d_stats, d_scores, counter, ws, nv, binned, stream);
+            break;
+        case REFINE_PROJ_DEPTH:
+            views_mode<REFINE_PROJ_DEPTH>(planes, stride, (int)n, prm, d_stats, d_scores, counter, ws, nv, binned,
+                                          stream);
+            break;
+        default:
+            views_mode<REFINE_PROJ_NONE>(planes, stride, (int)n, prm, d_stats, d_scores, counter, ws, nv, binned, stream);
+            break;
+        }
+    }
+    if (d_evaluated)
+        hipLaunchKernelGGL(counter_store, dim3(1), dim3(1), 0, stream, ws.evaluated, d_evaluated,
+                           binned ? (int64_t)-1 : n * (int64_t)nv);
     return hipGetLastError();
 }
 

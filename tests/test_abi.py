@@ -132,6 +132,21 @@ def test_score_validation(lib):
     assert call(wsb=100) == _lib.REFINE_E_WORKSPACE
 
 
+def test_two_phase_validation(lib):
+    from paper_2606_09074_amd import _lib
+    p = _lib.default_params()
+    E = _lib.REFINE_E_INVALID
+    sc = _scene()
+    assert lib.refine_score_prepare(ctypes.byref(sc), None, 16, ctypes.byref(p), FAKE, FAKE, 1 << 30, None) == E
+    assert lib.refine_score_prepare(ctypes.byref(sc), FAKE, 0, ctypes.byref(p), FAKE, FAKE, 1 << 30, None) == E
+    assert lib.refine_score_prepare(ctypes.byref(sc), FAKE, 16, ctypes.byref(p), None, FAKE, 1 << 30, None) == E
+    assert lib.refine_score_prepare(ctypes.byref(sc), FAKE, 16, ctypes.byref(p), FAKE, FAKE, 64,
+                                    None) == _lib.REFINE_E_WORKSPACE
+    assert lib.refine_score_views(ctypes.byref(sc), 16, ctypes.byref(p), FAKE, None, None, FAKE, 1 << 30, None) == E
+    assert lib.refine_score_views(ctypes.byref(sc), -1, ctypes.byref(p), FAKE, FAKE, None, FAKE, 1 << 30, None) == E
+    assert lib.refine_score_views(ctypes.byref(sc), 16, None, FAKE, FAKE, None, FAKE, 1 << 30, None) == E
+
+
 def test_select_validation(lib):
     from paper_2606_09074_amd import _lib
     E = _lib.REFINE_E_INVALID

@@ -325,3 +325,69 @@ def test_stats_bounding_box():
         v = mu[a][np.isfinite(mu[a])]
         assert r["stats"]["bbox_min"][a] == np.float32(v.min())
         assert r["stats"]["bbox_max"][a] == np.float32(v.max())
+
+
+@pytest.mark.parametrize("path", [1, 2])
+def test_two_phase_scoring(path):
+    """refine_score_prepare + refine_score_views (twice) equals refine_score;
+    the evaluated-pair count is n |V| on the direct path and at most that,
+    but positive, on the binned path."""
+    import torch
+
+    from paper_2606_09074_amd import _lib, api
+    planes, cams, _ = workload("medium")
+    n = 300_000
+    sub = np.ascontiguousarray(planes[:, :n])
+    ref = run_gpu(sub, cams, params=gpu_params(score_path=path))["scores"]
+    dev = torch.device("cuda:0")
+    pl = torch.from_numpy(sub).to(dev)
+    cm = torch.from_numpy(cams).to(dev)
+    ws = api.workspace(n, cams.shape[0], dev)
+    st = torch.empty(_lib.STATS_BYTES, dtype=torch.uint8, device=dev)
+    prm = gpu_params(score_path=path)
+    api.refine_stats(pl, st, ws, prm)
+    api.refine_score_prepare(pl, cm, st, ws, prm)
+    ev = torch.full((1,), -1, dtype=torch.int64, device=dev)
+    for _ in range(2):
+        out = torch.full((n,), float("nan"), dtype=torch.float32, device=dev)
+        api.refine_score_views(pl, cams.shape[0], st, out, ws, prm, evaluated_out=ev)
+        np.testing.assert_array_equal(out.cpu().numpy().view(np.uint32), ref.view(np.uint32))
+    total = n * cams.shape[0]
+    got = int(ev.item())
+    log(f"[two-phase path={path}] evaluated {got} of {total} pairs ({got / total:.3f})")
+    if path == 1:
+        assert got == total
+    else:
+        assert 0 < got < total
+
+
+@pytest.mark.parametrize("n,stride,mask_offset,cap_frac", [(9000, 9000, 0, 1.0), (8999, 9000, 0, 1.0),
+                                                          (8999, 9000, 0, 0.3), (9000, 9001, 0, 1.0),
+                                                          (9000, 9000, 1, 1.0), (4096 * 3, 4096 * 3, 0, 0.5)])
+def test_compact_vector_and_scalar_kernels(n, stride, mask_offset, cap_frac):
+    """The 16-byte path (aligned planes and mask) and the scalar fallback
+    (odd stride, unaligned mask) give the same bit-exact survivors."""
+    import torch
+
+    from paper_2606_09074_amd import api
+    from paper_2606_09074_amd import synth
+    planes = synth.make_planes(synth.SMALL.with_n(n), stride=stride)
+    dev = torch.device("cuda:0")
+    pl = torch.from_numpy(planes).to(dev)
+    keep_np = (np.random.default_rng(n + stride).random(n) < 0.45).astype(np.uint8)
+    buf = torch.zeros(n + 8, dtype=torch.uint8, device=dev)
+    keep = buf[mask_offset:mask_offset + n]
+    keep.copy_(torch.from_numpy(keep_np).to(dev))
+    sel = np.nonzero(keep_np)[0]
+    cap = int(sel.size * cap_frac)
+    out = torch.full((59, cap + 4), float("nan"), dtype=torch.float32, device=dev)
+    idx = torch.full((cap + 4,), -7, dtype=torch.int32, device=dev)
+    nout = torch.empty(1, dtype=torch.int64, device=dev)
+    ws = api.workspace(n, 1, dev)
+    api.refine_compact(pl, keep, out, ws, index_map_out=idx, n_out=nout, n=n, capacity=cap)
+    torch.cuda.synchronize()
+    assert int(nout.item()) == sel.size
+    o = out.cpu().numpy()
+    np.testing.assert_array_equal(o[:, :cap].view(np.uint32), planes[:, sel[:cap]].view(np.uint32))
+    np.testing.assert_array_equal(idx.cpu().numpy()[:cap], sel[:cap])
+    assert np.all(np.isnan(o[:, cap:])) and np.all(idx.cpu().numpy()[cap:] == -7)
