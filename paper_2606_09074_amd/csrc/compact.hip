@@ -1,9 +1,10 @@
 // Survivor compaction (paper Sec. 3.3: the pruned primitives are removed
 // and the rest written out) on gfx950.
 //
-// compact_count: kept primitives per 4096-primitive tile.  compact_scan: one
-// block turns the counts into exact tile offsets.  compact_scatter: one block
-// per tile finds each survivor's output position from wave ballots (the
+// compact_count: kept primitives per 4096-primitive tile.  compact_scatter:
+// one block per tile takes its output offset from the preceding tiles'
+// counts (compact_scan turns them into offsets first when there are very
+// many tiles), finds each survivor's output position from wave ballots (the
 // order inside the tile is the index order, so the copy is stable) and then
 // streams all 59 planes: each row of 256 consecutive primitives is one
 // coalesced load per plane, and the survivors of a row land in one
@@ -36,19 +37,38 @@ __global__ __launch_bounds__(kBlock) void compact_count(const uint8_t* __restric
 }
 
 __global__ __launch_bounds__(kScanThreads) void compact_scan(const uint32_t* __restrict__ tile_cnt,
-                                                               uint32_t* __restrict__ tile_off, int ntiles,
-                                                               int64_t* __restrict__ d_n_out)
+                                                               uint32_t* __restrict__ tile_off, int ntiles)
 {
-    const uint32_t total = block_exclusive_scan(tile_cnt, tile_off, ntiles);
-    if (threadIdx.x == 0 && d_n_out) *d_n_out = (int64_t)total;
+    block_exclusive_scan(tile_cnt, tile_off, ntiles);
+}
+
+__global__ void compact_empty(int64_t* __restrict__ d_n_out)
+{
+    if (d_n_out) *d_n_out = 0;
+}
+
+// Offset of this block's tile in the output: from compact_scan when there are
+// many tiles, else the sum of the preceding tiles' counts; block 0 also
+// reports the total number of survivors.
+__device__ inline int64_t tile_start(const uint32_t* __restrict__ tile_cnt, const uint32_t* __restrict__ tile_off,
+                                     int ntiles, int off_from_scan, int64_t* __restrict__ d_n_out)
+{
+    if (blockIdx.x == 0 && d_n_out) {
+        const uint64_t total = block_sum_prefix(tile_cnt, ntiles);
+        if (threadIdx.x == 0) *d_n_out = (int64_t)total;
+    }
+    return off_from_scan ? (int64_t)tile_off[blockIdx.x] : (int64_t)block_sum_prefix(tile_cnt, blockIdx.x);
 }
 
 __global__ __launch_bounds__(kBlock) void compact_scatter(const float* __restrict__ in, int64_t in_stride, int n,
                                                             const uint8_t* __restrict__ keep,
-                                                            const uint32_t* __restrict__ tile_off,
+                                                            const uint32_t* __restrict__ tile_cnt,
+                                                            const uint32_t* __restrict__ tile_off, int ntiles,
+                                                            int off_from_scan, int64_t* __restrict__ d_n_out,
                                                             float* __restrict__ out, int64_t out_stride,
                                                             int64_t capacity, int32_t* __restrict__ index_map)
 {
+    const int64_t tstart = tile_start(tile_cnt, tile_off, ntiles, off_from_scan, d_n_out);
     __shared__ uint32_t cnt[kItems][kWaves];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int base = blockIdx.x * kTile;
@@ -63,7 +83,7 @@ __global__ __launch_bounds__(kBlock) void compact_scatter(const float* __restric
     // output position of this lane's element in each row (or -1 when not written)
     int64_t pos[kItems];
     uint32_t kept_bits = 0;
-    int64_t row = (int64_t)tile_off[blockIdx.x];
+    int64_t row = tstart;
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
         uint32_t before = 0, tot = 0;
@@ -106,11 +126,13 @@ constexpr int kStagePlanes = 2;
 
 __global__ __launch_bounds__(kBlock) void compact_scatter_lds(const float* __restrict__ in, int64_t in_stride, int n,
                                                                 const uint8_t* __restrict__ keep,
-                                                                const uint32_t* __restrict__ tile_off,
                                                                 const uint32_t* __restrict__ tile_cnt,
+                                                                const uint32_t* __restrict__ tile_off, int ntiles,
+                                                                int off_from_scan, int64_t* __restrict__ d_n_out,
                                                                 float* __restrict__ out, int64_t out_stride,
                                                                 int64_t capacity, int32_t* __restrict__ index_map)
 {
+    const int64_t out0 = tile_start(tile_cnt, tile_off, ntiles, off_from_scan, d_n_out);
     __shared__ uint32_t wtot[kVecRows][kWaves];
     __shared__ float stage[kStagePlanes][kTile];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -153,7 +175,6 @@ __global__ __launch_bounds__(kBlock) void compact_scatter_lds(const float* __res
         lstart[r] = row + before + incl[r] - (uint32_t)__popc(flags[r]);
         row += tot;
     }
-    const int64_t out0 = (int64_t)tile_off[blockIdx.x];
     const int64_t room = capacity - out0;
     const int kept = (int)min((int64_t)tile_cnt[blockIdx.x], room > 0 ? room : (int64_t)0);
     if (index_map) {
@@ -211,18 +232,24 @@ hipError_t launch_compact(const float* in, int64_t in_stride, int64_t n, const u
                           const Workspace& ws, hipStream_t stream)
 {
     const int ntiles = (int)num_tiles(n);
-    if (ntiles > 0)
-        hipLaunchKernelGGL(compact_count, dim3(ntiles), dim3(kBlock), 0, stream, d_keep, (int)n, ws.tile_cnt);
-    hipLaunchKernelGGL(compact_scan, dim3(1), dim3(kScanThreads), 0, stream, ws.tile_cnt, ws.tile_off, ntiles,
-                       d_n_out);
+    if (ntiles == 0) {
+        hipLaunchKernelGGL(compact_empty, dim3(1), dim3(1), 0, stream, d_n_out);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(compact_count, dim3(ntiles), dim3(kBlock), 0, stream, d_keep, (int)n, ws.tile_cnt);
+    const int from_scan = ntiles > kPrefixTilesMax ? 1 : 0;
+    if (from_scan)
+        hipLaunchKernelGGL(compact_scan, dim3(1), dim3(kScanThreads), 0, stream, ws.tile_cnt, ws.tile_off, ntiles);
     const bool vec = (reinterpret_cast<uintptr_t>(in) % 16 == 0) && (in_stride % 4 == 0) &&
                      (reinterpret_cast<uintptr_t>(d_keep) % 4 == 0);
-    if (ntiles > 0 && vec)
+    if (vec)
         hipLaunchKernelGGL(compact_scatter_lds, dim3(ntiles), dim3(kBlock), 0, stream, in, in_stride, (int)n, d_keep,
-                           ws.tile_off, ws.tile_cnt, out, out_stride, capacity, d_index_map);
-    else if (ntiles > 0)
+                           ws.tile_cnt, ws.tile_off, ntiles, from_scan, d_n_out, out, out_stride, capacity,
+                           d_index_map);
+    else
         hipLaunchKernelGGL(compact_scatter, dim3(ntiles), dim3(kBlock), 0, stream, in, in_stride, (int)n, d_keep,
-                           ws.tile_off, out, out_stride, capacity, d_index_map);
+                           ws.tile_cnt, ws.tile_off, ntiles, from_scan, d_n_out, out, out_stride, capacity,
+                           d_index_map);
     return hipGetLastError();
 }
 

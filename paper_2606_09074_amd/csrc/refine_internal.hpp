@@ -169,19 +169,18 @@ namespace refine {
 
 constexpr int kScanThreads = 1024;
 
-// Exclusive prefix sum of cnt[0..m) into off[0..m) by one block of
-// kScanThreads threads (each thread scans a contiguous chunk); returns the
-// total in every thread.  Integer only, so the result is exact.
-__device__ inline uint32_t block_exclusive_scan(const uint32_t* __restrict__ cnt, uint32_t* __restrict__ off,
-                                                int m)
+// Exclusive prefix sum of cnt[0..m) into off[0..m) by one block of THREADS
+// threads (each thread scans a contiguous chunk); returns the total in every
+// thread.  Integer only, so the result is exact.
+template <int THREADS>
+__device__ inline uint32_t block_exclusive_scan_t(const uint32_t* __restrict__ cnt, uint32_t* __restrict__ off, int m)
 {
-    __shared__ uint32_t wave_tot[kScanThreads / 64];
-    const int chunk = (m + kScanThreads - 1) / kScanThreads;
+    __shared__ uint32_t wave_tot[THREADS / 64];
+    const int chunk = (m + THREADS - 1) / THREADS;
     const int lo = threadIdx.x * chunk;
     const int hi = min(lo + chunk, m);
     uint32_t local = 0;
     for (int j = lo; j < hi; ++j) local += cnt[j];
-    // inclusive scan of `local` across the wave
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     uint32_t incl = local;
 #pragma unroll
@@ -189,19 +188,47 @@ __device__ inline uint32_t block_exclusive_scan(const uint32_t* __restrict__ cnt
         const uint32_t y = __shfl_up(incl, o, 64);
         if (lane >= o) incl += y;
     }
+    __syncthreads();
     if (lane == 63) wave_tot[wave] = incl;
     __syncthreads();
     uint32_t before = 0, total = 0;
-    for (int w = 0; w < kScanThreads / 64; ++w) {
+    for (int w = 0; w < THREADS / 64; ++w) {
         if (w < wave) before += wave_tot[w];
         total += wave_tot[w];
     }
     uint32_t run = before + incl - local;
     for (int j = lo; j < hi; ++j) {
+        const uint32_t c = cnt[j];
         off[j] = run;
-        run += cnt[j];
+        run += c;
     }
     return total;
+}
+
+__device__ inline uint32_t block_exclusive_scan(const uint32_t* __restrict__ cnt, uint32_t* __restrict__ off, int m)
+{
+    return block_exclusive_scan_t<kScanThreads>(cnt, off, m);
+}
+
+// Tiles at most this many: a block finds its output offset by summing the
+// counts of the tiles before it (no separate scan launch).
+constexpr int kPrefixTilesMax = 4096;
+
+// Sum of cnt[0..m) by one block of kBlock threads; every thread gets it.
+__device__ inline uint64_t block_sum_prefix(const uint32_t* __restrict__ cnt, int m)
+{
+    __shared__ uint64_t part[kWaves];
+    uint64_t s = 0;
+    for (int t = threadIdx.x; t < m; t += kBlock) s += cnt[t];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+    __syncthreads();
+    uint64_t tot = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) tot += part[w];
+    return tot;
 }
 
 }  // namespace refine

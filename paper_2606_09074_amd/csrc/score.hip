@@ -56,11 +56,13 @@ constexpr int64_t kBinnedMinPrims = 65536;
 #endif
 constexpr int kBinnedPPL = REFINE_BINNED_PPL;   // binned records per lane
 
+// Also clears the binning cell counts (cell_cnt is null on the direct path).
 __global__ __launch_bounds__(kBlock) void camera_prep(const float* __restrict__ cams, int n_views, int nv,
                                                         float clamp_k, CamRec* __restrict__ out,
-                                                        CullRec* __restrict__ cull)
+                                                        CullRec* __restrict__ cull, uint32_t* __restrict__ cell_cnt)
 {
     const int j = blockIdx.x * kBlock + threadIdx.x;
+    if (cell_cnt && j < kCells) cell_cnt[j] = 0u;
     if (j >= nv) return;
     const int v = (nv == n_views) ? j : (int)(((int64_t)j * n_views) / nv);
     const float* c = cams + (int64_t)v * kCamFields;
@@ -250,12 +252,6 @@ __device__ inline uint32_t cell_of(float x, float y, float z, const refine_stats
     return spread_bits(q[0]) | (spread_bits(q[1]) << 1) | (spread_bits(q[2]) << 2);
 }
 
-__global__ __launch_bounds__(kBlock) void bin_zero(uint32_t* __restrict__ cnt)
-{
-    const int c = blockIdx.x * kBlock + threadIdx.x;
-    if (c < kCells) cnt[c] = 0u;
-}
-
 // Binning tiles are the 4096-primitive tiles of the other kernels.  Each
 // tile counts its cells in LDS and touches the global cell arrays once per
 // occupied cell, in cell order (consecutive lanes hit consecutive counters,
@@ -285,6 +281,7 @@ __global__ __launch_bounds__(kBlock) void bin_hist(const float* __restrict__ pla
     }
 }
 
+// Cell offsets: exclusive scan of the counts (one block).
 __global__ __launch_bounds__(kScanThreads) void bin_scan(const uint32_t* __restrict__ cnt, uint32_t* __restrict__ cur)
 {
     block_exclusive_scan(cnt, cur, kCells);
@@ -459,7 +456,6 @@ void prepare_mode(const float* planes, int64_t stride, int n, const refine_param
     const int vis = prm.vis_mode == REFINE_VIS_ALPHA ? 1 : 0;
     const dim3 grid((unsigned)((n + kBlock - 1) / kBlock));
     const dim3 tiles((unsigned)num_tiles(n));
-    hipLaunchKernelGGL(bin_zero, dim3((kCells + kBlock - 1) / kBlock), dim3(kBlock), 0, stream, ws.cell_cnt);
     hipLaunchKernelGGL(bin_hist, tiles, dim3(kBlock), 0, stream, planes, stride, n, d_stats, ws.cell_cnt);
     hipLaunchKernelGGL(bin_scan, dim3(1), dim3(kScanThreads), 0, stream, ws.cell_cnt, ws.cell_cur);
     hipLaunchKernelGGL(bin_rank, tiles, dim3(kBlock), 0, stream, planes, stride, n, d_stats, ws.cell_cur, ws.dest);
@@ -501,9 +497,11 @@ hipError_t launch_score_prepare(const float* planes, int64_t stride, int64_t n, 
                                 hipStream_t stream)
 {
     const int nv = views_of(prm, n_views);
-    hipLaunchKernelGGL(camera_prep, dim3((nv + kBlock - 1) / kBlock), dim3(kBlock), 0, stream, d_cams, n_views, nv,
-                       (float)prm.clamp_k, ws.cams, ws.culls);
-    if (n == 0 || !binned_path(prm, n)) return hipGetLastError();
+    const bool binned = n > 0 && binned_path(prm, n);
+    const int threads = binned ? (nv > kCells ? nv : kCells) : nv;
+    hipLaunchKernelGGL(camera_prep, dim3((threads + kBlock - 1) / kBlock), dim3(kBlock), 0, stream, d_cams, n_views, nv,
+                       (float)prm.clamp_k, ws.cams, ws.culls, binned ? ws.cell_cnt : nullptr);
+    if (!binned) return hipGetLastError();
     switch (prm.proj_mode) {
     case REFINE_PROJ_COV: prepare_mode<REFINE_PROJ_COV>(planes, stride, (int)n, prm, d_stats, ws, nv, stream); break;
     case REFINE_PROJ_DEPTH: prepare_mode<REFINE_PROJ_DEPTH>(planes, stride, (int)n, prm, d_stats, ws, nv, stream); break;

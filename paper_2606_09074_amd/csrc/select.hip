@@ -2,14 +2,19 @@
 //
 // Scores become order-preserving 32-bit keys.  The key of the n_prune-th
 // smallest primitive (the threshold T) is found by three most-significant-
-// digit-first radix passes (11, 11, 10 bits): each pass histograms the keys
-// that share the already-resolved prefix into per-wave LDS histograms,
+// digit-first radix passes (11, 11, 10 bits).  Each pass histograms, into
+// per-wave LDS histograms, the keys that share the prefix resolved so far,
 // merges them into one global histogram with integer atomics (exact and
-// order-independent), and a single-block pass picks the bucket that holds
-// the target rank.  Ties at T are broken by index: the pruned primitives are
-// every key < T plus the k_eq lowest-index keys == T, located with wave
-// ballots and an exact prefix over tiles.  Integer arithmetic throughout, so
-// the mask equals a stable sort by (score, index).
+// order-independent), and a one-block pass scans that histogram and picks
+// the bucket holding the target rank.  (Folding that pass into the last
+// histogram block would need a device-scope fence per block, which on this
+// multi-die part writes back the L2: a separate launch is cheaper.)  Ties at T are broken by
+// index: the pruned primitives are every key < T plus the k_eq lowest-index
+// keys == T, located with wave ballots and the exact count of equal keys in
+// the tiles before.  Integer arithmetic throughout, so the mask equals a
+// stable sort by (score, index).
+//
+// Launches: init, 3 x (histogram, find), count, mask.
 #include "refine_internal.hpp"
 
 namespace refine {
@@ -18,6 +23,7 @@ namespace {
 
 constexpr int kPassShift[3] = {21, 10, 0};
 constexpr int kPassBits[3] = {11, 11, 10};
+constexpr int kHistBlocksMax = 512;   // grid of the histogram passes (each block loops over tiles)
 
 __global__ void select_init(SelectState* __restrict__ st, uint32_t* __restrict__ hist, int64_t n, int64_t n_prune)
 {
@@ -36,40 +42,15 @@ __global__ void select_init(SelectState* __restrict__ st, uint32_t* __restrict__
     }
 }
 
-__global__ __launch_bounds__(kBlock) void select_hist(const float* __restrict__ scores, int n,
-                                                        const SelectState* __restrict__ st, int shift, int bits,
-                                                        uint32_t* __restrict__ hist)
-{
-    __shared__ uint32_t h[kWaves][kHistBins];
-    const int wave = threadIdx.x >> 6;
-    for (int b = threadIdx.x; b < kWaves * kHistBins; b += kBlock) (&h[0][0])[b] = 0u;
-    __syncthreads();
-    const uint32_t prefix = st->prefix, mask = st->mask;
-    const uint32_t dmask = (1u << bits) - 1u;
-    const int base = blockIdx.x * kTile;
-#pragma unroll 4
-    for (int k = 0; k < kItems; ++k) {
-        const int i = base + k * kBlock + (int)threadIdx.x;
-        if (i < n) {
-            const uint32_t key = float_key(scores[i]);
-            if ((key & mask) == prefix) atomicAdd(&h[wave][(key >> shift) & dmask], 1u);
-        }
-    }
-    __syncthreads();
-    for (int b = threadIdx.x; b <= (int)dmask; b += kBlock) {
-        uint32_t c = 0;
-#pragma unroll
-        for (int w = 0; w < kWaves; ++w) c += h[w][b];
-        if (c) atomicAdd(&hist[b], c);
-    }
-}
-
+// Locate the bucket holding the target rank, fold it into the prefix, clear
+// the histogram for the next pass (one block).
 __global__ __launch_bounds__(kBlock) void select_find(SelectState* __restrict__ st, uint32_t* __restrict__ hist,
-                                                        int shift, int bits, int last)
+                                                        int shift, int bits, int last_pass)
 {
     constexpr int kPer = kHistBins / kBlock;   // 8 bins per thread
     __shared__ uint32_t wave_tot[kWaves];
-    // read before the barrier: the thread that finds the bucket rewrites the state after it
+    __shared__ int64_t found_run;
+    __shared__ int found_bin;
     const int64_t rank = st->rank;
     const int nb = 1 << bits;
     uint32_t h[kPer];
@@ -88,6 +69,7 @@ __global__ __launch_bounds__(kBlock) void select_find(SelectState* __restrict__ 
         if (lane >= o) incl += y;
     }
     if (lane == 63) wave_tot[wave] = incl;
+    if (threadIdx.x == 0) found_bin = -1;
     __syncthreads();
     uint32_t before = 0;
     for (int w = 0; w < wave; ++w) before += wave_tot[w];
@@ -95,22 +77,56 @@ __global__ __launch_bounds__(kBlock) void select_find(SelectState* __restrict__ 
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
         const int b = threadIdx.x * kPer + j;
-        if (rank >= run && rank < run + (int64_t)h[j]) {
-            SelectState s = *st;
-            s.prefix |= (uint32_t)b << shift;
-            s.mask |= ((1u << bits) - 1u) << shift;
-            s.rank = rank - run;
-            if (last) {
-                s.threshold = s.prefix;
-                s.k_eq = s.rank + 1;
-            }
-            *st = s;
+        if (rank >= run && rank < run + (int64_t)h[j]) {   // exactly one bin of one thread
+            found_bin = b;
+            found_run = run;
         }
         run += h[j];
     }
-    // every thread has read its bins before the barrier above: clear for the next pass
 #pragma unroll
     for (int j = 0; j < kPer; ++j) hist[threadIdx.x * kPer + j] = 0u;
+    __syncthreads();
+    if (threadIdx.x == 0 && found_bin >= 0) {
+        SelectState s = *st;
+        s.prefix |= (uint32_t)found_bin << shift;
+        s.mask |= ((1u << bits) - 1u) << shift;
+        s.rank = rank - found_run;
+        if (last_pass) {
+            s.threshold = s.prefix;
+            s.k_eq = s.rank + 1;
+        }
+        *st = s;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void select_hist(const float* __restrict__ scores, int n, int ntiles,
+                                                        const SelectState* __restrict__ st, int shift, int bits,
+                                                        uint32_t* __restrict__ hist)
+{
+    __shared__ uint32_t h[kWaves][kHistBins];
+    const int wave = threadIdx.x >> 6;
+    for (int b = threadIdx.x; b < kWaves * kHistBins; b += kBlock) (&h[0][0])[b] = 0u;
+    __syncthreads();
+    const uint32_t prefix = st->prefix, mask = st->mask;
+    const uint32_t dmask = (1u << bits) - 1u;
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int base = tile * kTile;
+#pragma unroll 4
+        for (int k = 0; k < kItems; ++k) {
+            const int i = base + k * kBlock + (int)threadIdx.x;
+            if (i < n) {
+                const uint32_t key = float_key(scores[i]);
+                if ((key & mask) == prefix) atomicAdd(&h[wave][(key >> shift) & dmask], 1u);
+            }
+        }
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b <= (int)dmask; b += kBlock) {
+        uint32_t c = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) c += h[w][b];
+        if (c) atomicAdd(&hist[b], c);
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void select_count(const float* __restrict__ scores, int n,
@@ -137,26 +153,29 @@ __global__ __launch_bounds__(kBlock) void select_count(const float* __restrict__
 }
 
 __global__ __launch_bounds__(kScanThreads) void select_scan(const uint32_t* __restrict__ tile_cnt,
-                                                              uint32_t* __restrict__ tile_off, int ntiles,
-                                                              const SelectState* __restrict__ st,
-                                                              int64_t* __restrict__ d_n_keep,
-                                                              uint32_t* __restrict__ d_threshold)
+                                                              uint32_t* __restrict__ tile_off, int ntiles)
 {
     block_exclusive_scan(tile_cnt, tile_off, ntiles);
-    if (threadIdx.x == 0) {
-        if (d_n_keep) *d_n_keep = st->n_keep;
-        if (d_threshold) *d_threshold = st->threshold;
-    }
 }
 
+// off_from_scan: the tile offsets come from select_scan (many tiles) instead
+// of a per-block sum of the preceding tiles' counts.
 __global__ __launch_bounds__(kBlock) void select_mask(const float* __restrict__ scores, int n,
                                                         const SelectState* __restrict__ st,
-                                                        const uint32_t* __restrict__ tile_off,
-                                                        uint8_t* __restrict__ keep)
+                                                        const uint32_t* __restrict__ tile_cnt,
+                                                        const uint32_t* __restrict__ tile_off, int off_from_scan,
+                                                        uint8_t* __restrict__ keep, int64_t* __restrict__ d_n_keep,
+                                                        uint32_t* __restrict__ d_threshold)
 {
     __shared__ uint32_t cnt[kItems][kWaves];
     const uint32_t T = st->threshold;
     const int64_t k_eq = st->k_eq;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (d_n_keep) *d_n_keep = st->n_keep;
+        if (d_threshold) *d_threshold = T;
+    }
+    const int64_t tile_start = off_from_scan ? (int64_t)tile_off[blockIdx.x]
+                                             : (int64_t)block_sum_prefix(tile_cnt, blockIdx.x);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int base = blockIdx.x * kTile;
     uint32_t key[kItems];
@@ -169,7 +188,7 @@ __global__ __launch_bounds__(kBlock) void select_mask(const float* __restrict__ 
         if (lane == 0) cnt[k][wave] = (uint32_t)__popcll(eqb[k]);
     }
     __syncthreads();
-    int64_t row = (int64_t)tile_off[blockIdx.x];
+    int64_t row = tile_start;
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
         const int i = base + k * kBlock + (int)threadIdx.x;
@@ -186,6 +205,13 @@ __global__ __launch_bounds__(kBlock) void select_mask(const float* __restrict__ 
     }
 }
 
+__global__ void select_outputs(const SelectState* __restrict__ st, int64_t* __restrict__ d_n_keep,
+                               uint32_t* __restrict__ d_threshold)
+{
+    if (d_n_keep) *d_n_keep = st->n_keep;
+    if (d_threshold) *d_threshold = st->threshold;
+}
+
 }  // namespace
 
 hipError_t launch_select(const float* d_scores, int64_t n, int64_t n_prune, uint8_t* d_keep, int64_t* d_n_keep,
@@ -193,22 +219,25 @@ hipError_t launch_select(const float* d_scores, int64_t n, int64_t n_prune, uint
 {
     const int ntiles = (int)num_tiles(n);
     hipLaunchKernelGGL(select_init, dim3(1), dim3(kBlock), 0, stream, ws.sel, ws.hist, n, n_prune);
+    if (ntiles == 0) {
+        hipLaunchKernelGGL(select_outputs, dim3(1), dim3(1), 0, stream, ws.sel, d_n_keep, d_threshold);
+        return hipGetLastError();
+    }
     if (n_prune > 0) {
+        const int hb = ntiles < kHistBlocksMax ? ntiles : kHistBlocksMax;
         for (int p = 0; p < 3; ++p) {
-            hipLaunchKernelGGL(select_hist, dim3(ntiles), dim3(kBlock), 0, stream, d_scores, (int)n, ws.sel,
+            hipLaunchKernelGGL(select_hist, dim3(hb), dim3(kBlock), 0, stream, d_scores, (int)n, ntiles, ws.sel,
                                kPassShift[p], kPassBits[p], ws.hist);
             hipLaunchKernelGGL(select_find, dim3(1), dim3(kBlock), 0, stream, ws.sel, ws.hist, kPassShift[p],
                                kPassBits[p], p == 2 ? 1 : 0);
         }
     }
-    if (ntiles > 0)
-        hipLaunchKernelGGL(select_count, dim3(ntiles), dim3(kBlock), 0, stream, d_scores, (int)n, ws.sel,
-                           ws.tile_cnt);
-    hipLaunchKernelGGL(select_scan, dim3(1), dim3(kScanThreads), 0, stream, ws.tile_cnt, ws.tile_off, ntiles, ws.sel,
-                       d_n_keep, d_threshold);
-    if (ntiles > 0)
-        hipLaunchKernelGGL(select_mask, dim3(ntiles), dim3(kBlock), 0, stream, d_scores, (int)n, ws.sel,
-                           ws.tile_off, d_keep);
+    hipLaunchKernelGGL(select_count, dim3(ntiles), dim3(kBlock), 0, stream, d_scores, (int)n, ws.sel, ws.tile_cnt);
+    const int from_scan = ntiles > kPrefixTilesMax ? 1 : 0;
+    if (from_scan)
+        hipLaunchKernelGGL(select_scan, dim3(1), dim3(kScanThreads), 0, stream, ws.tile_cnt, ws.tile_off, ntiles);
+    hipLaunchKernelGGL(select_mask, dim3(ntiles), dim3(kBlock), 0, stream, d_scores, (int)n, ws.sel, ws.tile_cnt,
+                       ws.tile_off, from_scan, d_keep, d_n_keep, d_threshold);
     return hipGetLastError();
 }
 
