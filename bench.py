@@ -39,6 +39,42 @@ def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
 
+# Sources of the view-loop kernels: HBM traffic measured with rocprofv3
+# counters is reported only while these are unchanged.
+KERNEL_SOURCES = ("paper_2606_09074_amd/csrc/score.hip", "paper_2606_09074_amd/csrc/refine_internal.hpp")
+
+
+def kernel_sources_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def profiled_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    counter summary (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, see
+    profiles/copy-1GiB_traffic-calibration.md), or None when there is none or
+    the kernel sources changed after it was taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and line.split(":", 1)[0].strip() in ("sources_sha256", "hbm_bytes_per_launch"):
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip().strip("`")
+    if fields.get("sources_sha256") != kernel_sources_sha256():
+        return None
+    try:
+        return int(fields["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -159,9 +195,11 @@ def main() -> int:
     # actually performed, over its event-timed duration
     t_views = avg["views"] / 1e3
     achieved_tflops = FLOP_PER_PAIR[params.proj_mode] * n_eval / t_views / 1e12
-    roofline = {"bound": "alu", "kernel": "score_binned" if n_eval < n * V else "score_direct",
+    kname = "score_binned" if n_eval < n * V else "score_direct"
+    traffic = profiled_traffic(kname, spec.name) if params.proj_mode == 0 else None
+    roofline = {"bound": "alu", "kernel": kname,
                 "achieved": round(achieved_tflops, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved_tflops / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                "frac": round(achieved_tflops / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
                 "flop_per_pair": FLOP_PER_PAIR[params.proj_mode], "pairs_evaluated": n_eval,
                 "pairs_total": n * V, "views_ms": round(avg["views"], 4), "prepare_ms": round(avg["prepare"], 4)}
     cpu = None

@@ -71,7 +71,7 @@ size_t workspace_layout(int64_t n, int32_t n_views, bool score, void* base, Work
     const size_t o_cnt = off;   off += align_up(sizeof(uint32_t) * nt);
     const size_t o_toff = off;  off += align_up(sizeof(uint32_t) * nt);
     // sections only refine_score uses come last, so the other calls need a prefix only
-    const size_t o_eval = off;  off += score ? align_up(sizeof(unsigned long long)) : 0;
+    const size_t o_eval = off;  off += score ? align_up(sizeof(unsigned long long) * kEvalSlots) : 0;
     const size_t o_cams = off;  off += score ? align_up(sizeof(CamRec) * nv) : 0;
     const size_t o_cull = off;  off += score ? align_up(sizeof(CullRec) * nv) : 0;
     const size_t o_ccnt = off;  off += score ? align_up(sizeof(uint32_t) * kCells) : 0;

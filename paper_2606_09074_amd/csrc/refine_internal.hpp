@@ -73,6 +73,8 @@ struct PrimRec {
 };
 static_assert(sizeof(PrimRec) == 64, "primitive record size");
 
+constexpr int kEvalSlots = 64;                     // counters the evaluated pairs are spread over
+
 constexpr int kCellBits = 4;                       // per axis
 constexpr int kCells = 1 << (3 * kCellBits);       // 4096 Morton cells (16 KB of LDS counters)
 
@@ -89,7 +91,7 @@ struct Workspace {
     uint32_t* cell_cur;      // [kCells]
     uint32_t* dest;          // [n] binned position of each primitive
     PrimRec* recs;           // [n]
-    unsigned long long* evaluated;   // pairs evaluated by the last view loop
+    unsigned long long* evaluated;   // [kEvalSlots] pairs evaluated by the last view loop
 };
 
 inline int64_t num_tiles(int64_t n) { return (n + kTile - 1) / kTile; }

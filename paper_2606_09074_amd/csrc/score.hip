@@ -126,6 +126,15 @@ struct Prim {
     float S;
 };
 
+// The evaluation constants of a camera record (its first 80 bytes), held in
+// vector registers.
+struct CamEval {
+    float px[4], py[4], pz[4];
+    float ox, oy, hw, hh, lx, ly;
+};
+constexpr int kStageVec = 5;   // float4s staged per view
+static_assert(offsetof(CamRec, ly) + sizeof(float) <= kStageVec * sizeof(float4), "staged camera fields");
+
 // Activation (Sec. 3.1 readings) of primitive i; pre is the epilogue factor.
 __device__ inline void activate(const float* __restrict__ planes, int64_t stride, int i, Prim& p, float& pre,
                                 float& smax, const refine_stats_t* __restrict__ st, int proj, int vis_alpha, int nv)
@@ -167,8 +176,8 @@ __device__ inline void activate(const float* __restrict__ planes, int64_t stride
     if (proj == REFINE_PROJ_COV) pre = pre / sbar2;
 }
 
-template <int PROJ>
-__device__ __forceinline__ void eval_pair(const CamRec& c, Prim& p, float eta, float z_near)
+template <int PROJ, class Cam>
+__device__ __forceinline__ void eval_pair(const Cam& c, Prim& p, float eta, float z_near)
 {
     const float X = fmaf(c.px[0], p.mx, fmaf(c.px[1], p.my, fmaf(c.px[2], p.mz, c.px[3])));
     const float Y = fmaf(c.py[0], p.mx, fmaf(c.py[1], p.my, fmaf(c.py[2], p.mz, c.py[3])));
@@ -207,7 +216,10 @@ __device__ __forceinline__ void eval_pair(const CamRec& c, Prim& p, float eta, f
     const float dz = d * z;
     const float e1 = sa - sc;
     const float w = ss + __builtin_amdgcn_sqrtf(fmaf(e1, e1, 4.0f * sb * sb));
-    const bool g = (z > z_near) && ((dz < 0.0f) || (fmaf(w, -4.5f, dz * dz) < 0.0f));
+    const float t = fmaf(w, -4.5f, dz * dz);
+    // dz < 0 or t < 0, as one compare: t is NaN whenever dz is, and fminf
+    // returns the other operand when exactly one is NaN
+    const bool g = (z > z_near) && (fminf(dz, t) < 0.0f);
     p.S += g ? P : 0.0f;
 }
 
@@ -351,17 +363,27 @@ __global__ __launch_bounds__(kBlock) void bin_scatter(const float* __restrict__ 
     if (pos < (uint32_t)n) recs[pos] = r;   // always true: the ranks are a permutation of [0, n)
 }
 
-// May any primitive of the wave's sphere be visible in this view?
-__device__ inline bool cull_pass(const CullRec& q, float cx, float cy, float cz, float rm, float sg, float ca,
-                                 float z_near)
+// May any primitive of the wave's group be visible in this view?  The group's
+// centres lie in the box c +- h and in the sphere |x - c| <= rm; the largest
+// value of n . x over that set is at most n . c + min(|n_0| h_0 + |n_1| h_1 +
+// |n_2| h_2, rm |n|).
+__device__ inline float support(float n0, float n1, float n2, float nn, float hx, float hy, float hz, float rm)
+{
+    return fminf(fmaf(fabsf(n0), hx, fmaf(fabsf(n1), hy, fabsf(n2) * hz)), rm * nn);
+}
+
+__device__ inline bool cull_pass(const CullRec& q, float cx, float cy, float cz, float hx, float hy, float hz,
+                                 float rm, float sg, float ca, float z_near)
 {
     const float depth = fmaf(q.nz[0], cx, fmaf(q.nz[1], cy, fmaf(q.nz[2], cz, q.nz[3])));
-    bool ok = depth + rm + 1e-4f * (ca + fabsf(q.nz[3])) > z_near;
+    bool ok = depth + support(q.nz[0], q.nz[1], q.nz[2], 1.0f, hx, hy, hz, rm) + 1e-4f * (ca + fabsf(q.nz[3])) >
+              z_near;
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
         const float val = fmaf(q.side[s][0], cx, fmaf(q.side[s][1], cy, fmaf(q.side[s][2], cz, q.side[s][3])));
         const float slack = 1e-4f * (q.nn[s] * (ca + 1.0f) + fabsf(q.side[s][3]));
-        ok = ok && (val + rm * q.nn[s] + sg * q.kv3 + slack > 0.0f);
+        const float sup = support(q.side[s][0], q.side[s][1], q.side[s][2], q.nn[s], hx, hy, hz, rm);
+        ok = ok && (val + sup + sg * q.kv3 + slack > 0.0f);
     }
     return ok;
 }
@@ -404,9 +426,14 @@ __global__ __launch_bounds__(kBlock) void score_binned(const PrimRec* __restrict
         lo[1] = fminf(lo[1], p[k].my); hi[1] = fmaxf(hi[1], p[k].my);
         lo[2] = fminf(lo[2], p[k].mz); hi[2] = fmaxf(hi[2], p[k].mz);
     }
-    const float cx = 0.5f * (wave_min(lo[0]) + wave_max(hi[0]));
-    const float cy = 0.5f * (wave_min(lo[1]) + wave_max(hi[1]));
-    const float cz = 0.5f * (wave_min(lo[2]) + wave_max(hi[2]));
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = wave_min(lo[a]);
+        hi[a] = wave_max(hi[a]);
+    }
+    const float cx = 0.5f * (lo[0] + hi[0]);
+    const float cy = 0.5f * (lo[1] + hi[1]);
+    const float cz = 0.5f * (lo[2] + hi[2]);
     float d2 = 0.0f;
 #pragma unroll
     for (int k = 0; k < PPL; ++k) {
@@ -414,39 +441,76 @@ __global__ __launch_bounds__(kBlock) void score_binned(const PrimRec* __restrict
         d2 = fmaxf(d2, dx * dx + dy * dy + dz * dz);
     }
     const float ca = fabsf(cx) + fabsf(cy) + fabsf(cz);
-    const float rm = sqrtf(wave_max(d2)) * kCullMargin + 1e-4f * (ca + 1.0f);
+    const float abs_m = 1e-4f * (ca + 1.0f);
+    const float rm = sqrtf(wave_max(d2)) * kCullMargin + abs_m;
+    const float hx = 0.5f * (hi[0] - lo[0]) * kCullMargin + abs_m;
+    const float hy = 0.5f * (hi[1] - lo[1]) * kCullMargin + abs_m;
+    const float hz = 0.5f * (hi[2] - lo[2]) * kCullMargin + abs_m;
     const float sg = wave_max(smax);
     // a non-finite bound (non-finite input) disables culling for this group
     const bool no_cull = !(rm < INFINITY) || !(sg < INFINITY) || !(ca < INFINITY);
+    // the evaluation constants of the views this wave evaluates, staged in
+    // LDS so that every camera operand of the pair arithmetic is a vector
+    // register (an instruction may read only one scalar register)
+    __shared__ float4 stage[kWaves][64 * kStageVec];
+    float4* const my = stage[threadIdx.x >> 6];
     uint32_t n_eval = 0;
     for (int v0 = 0; v0 < nv; v0 += 64) {
         const int v = v0 + lane;
         bool vis = false;
-        if (v < nv) vis = no_cull || cull_pass(culls[v], cx, cy, cz, rm, sg, ca, z_near);
-        uint64_t m = __ballot(vis);
-        n_eval += (uint32_t)__popcll(m);
-        while (m) {
-            const int b = __builtin_ctzll(m);
-            m &= m - 1;
-            const CamRec& c = cams[v0 + b];
+        if (v < nv) vis = no_cull || cull_pass(culls[v], cx, cy, cz, hx, hy, hz, rm, sg, ca, z_near);
+        const uint64_t m = __ballot(vis);
+        if (vis) {
+            // visible views packed in increasing view order
+            const float4* src = reinterpret_cast<const float4*>(cams + v);
+            float4* dst = my + lanes_below(m) * kStageVec;
+#pragma unroll
+            for (int k = 0; k < kStageVec; ++k) dst[k] = src[k];
+        }
+        // the writes above precede the reads below (LDS requests of one wave
+        // complete in order; the fences keep the compiler from moving them)
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        const int cnt = __popcll(m);
+        n_eval += (uint32_t)cnt;
+        for (int j = 0; j < cnt; ++j) {
+            CamEval c;
+            const float4* r = my + j * kStageVec;
+            const float4 r0 = r[0], r1 = r[1], r2 = r[2], r3 = r[3], r4 = r[4];
+            c.px[0] = r0.x; c.px[1] = r0.y; c.px[2] = r0.z; c.px[3] = r0.w;
+            c.py[0] = r1.x; c.py[1] = r1.y; c.py[2] = r1.z; c.py[3] = r1.w;
+            c.pz[0] = r2.x; c.pz[1] = r2.y; c.pz[2] = r2.z; c.pz[3] = r2.w;
+            c.ox = r3.x; c.oy = r3.y; c.hw = r3.z; c.hh = r3.w;
+            c.lx = r4.x; c.ly = r4.y;
 #pragma unroll
             for (int k = 0; k < PPL; ++k) eval_pair<PROJ>(c, p[k], eta, z_near);
         }
+        // every lane's reads of this batch precede the next batch's writes
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     }
 #pragma unroll
     for (int k = 0; k < PPL; ++k)
         if (idx[k] >= 0) out[idx[k]] = pre[k] * p[k].S;
     if (evaluated && lane == 0) {
         const int valid = max(0, min(64 * PPL, n - g0));   // records of this group
-        atomicAdd(evaluated, (unsigned long long)n_eval * (unsigned long long)valid);
+        const int slot = (g0 / (64 * PPL)) % kEvalSlots;   // spread: one address would serialise the waves
+        atomicAdd(evaluated + slot, (unsigned long long)n_eval * (unsigned long long)valid);
     }
 }
 
-__global__ void counter_reset(unsigned long long* c) { *c = 0ull; }
+__global__ void counter_reset(unsigned long long* c)
+{
+    if (threadIdx.x < kEvalSlots) c[threadIdx.x] = 0ull;
+}
 
 __global__ void counter_store(const unsigned long long* c, int64_t* out, int64_t direct_pairs)
 {
-    *out = direct_pairs >= 0 ? direct_pairs : (int64_t)*c;
+    unsigned long long t = 0;
+    for (int s = 0; s < kEvalSlots; ++s) t += c[s];
+    *out = direct_pairs >= 0 ? direct_pairs : (int64_t)t;
 }
 
 template <int PROJ>
@@ -517,7 +581,7 @@ hipError_t launch_score_views(const float* planes, int64_t stride, int64_t n, in
     const int nv = views_of(prm, n_views);
     const bool binned = binned_path(prm, n);
     unsigned long long* counter = (d_evaluated && binned) ? ws.evaluated : nullptr;
-    if (counter) hipLaunchKernelGGL(counter_reset, dim3(1), dim3(1), 0, stream, counter);
+    if (counter) hipLaunchKernelGGL(counter_reset, dim3(1), dim3(kEvalSlots), 0, stream, counter);
     if (n > 0) {
         switch (prm.proj_mode) {
         case REFINE_PROJ_COV:
