@@ -84,6 +84,8 @@ def main() -> int:
     ap.add_argument("--ratio", type=float, default=None)
     ap.add_argument("--score-path", default="auto", choices=["auto", "direct", "binned"],
                     help="refine_score scheduling (results are bit-identical across paths)")
+    ap.add_argument("--storage", default="f32", choices=["f32", "bf16-f16"],
+                    help="scene storage: FP32 planes, or BF16 geometry/opacity + FP16 SH (arithmetic is FP32 either way)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (3 times) and exit: the reference "
@@ -119,10 +121,15 @@ def main() -> int:
     log(f"bench: generating {spec.name} (n={spec.n}, V={spec.n_views}), ratio {ratio}")
     planes_np = synth.make_planes(spec)
     cams_np = synth.make_cameras(spec)
+    if args.storage == "bf16-f16":
+        stored_np = synth.quantize_bf16_f16(planes_np)
+        planes_np = synth.dequantize_bf16_f16(stored_np)   # the values the 2-byte scene holds
+    else:
+        stored_np = planes_np
     n, V = spec.n, cams_np.shape[0]
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
-    planes = torch.from_numpy(planes_np).to(dev)
+    planes = torch.from_numpy(stored_np).to(dev)
     cams = torch.from_numpy(cams_np).to(dev)
     params = _lib.default_params()
     params.score_path = {"auto": _lib.PATH_AUTO, "direct": _lib.PATH_DIRECT, "binned": _lib.PATH_BINNED}[args.score_path]
@@ -132,7 +139,7 @@ def main() -> int:
     keep = torch.empty(n, dtype=torch.uint8, device=dev)
     n_keep = torch.empty(1, dtype=torch.int64, device=dev)
     cap = n - api.prune_count(n, ratio)
-    out = torch.empty((59, max(cap, 1)), dtype=torch.float32, device=dev)
+    out = torch.empty((59, max(cap, 1)), dtype=planes.dtype, device=dev)
     idx = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
     torch.cuda.synchronize()
 
@@ -223,7 +230,7 @@ def main() -> int:
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
             "data": "synthetic",
-            "config": {"workload": spec.name, "n": n, "views": V, "ratio": ratio,
+            "config": {"workload": spec.name, "n": n, "views": V, "ratio": ratio, "storage": args.storage,
                        "step": "stats+score+select+compact", "score_path": args.score_path,
                        "ms_per_prune": round(ms_per_step, 4)},
             "phases_ms": {k: round(v, 4) for k, v in avg.items()},

@@ -42,8 +42,9 @@ typedef enum {
     REFINE_E_HIP = -4           /* a HIP launch failed */
 } refine_status;
 
-/* Storage type of the scene planes. */
-typedef enum { REFINE_F32 = 0 } refine_dtype;
+/* Storage type of scene planes.  Arithmetic is FP32 whatever the storage:
+ * BF16 and FP16 values are widened exactly on load. */
+typedef enum { REFINE_F32 = 0, REFINE_BF16 = 1, REFINE_F16 = 2 } refine_dtype;
 
 /* Projection term of the per-view Hessian weight (Eq. 14-17). */
 typedef enum {
@@ -60,20 +61,24 @@ typedef enum {
 } refine_vis_mode;
 
 /*
- * A scene of n Gaussians stored attribute-major: planes[59][stride] of
- * `dtype`, plane p of primitive i at planes[p * stride + i].  Planes:
+ * A scene of n Gaussians stored attribute-major: 59 planes of `stride`
+ * elements each, plane p of primitive i at element p * stride + i.  Planes:
  *   0..2 centre x,y,z | 3..5 log-scale | 6..9 quaternion w,x,y,z (any norm;
  *   zero = identity) | 10 opacity logit | 11..13 SH DC r,g,b | 14..58 higher
  *   SH coefficients.
- * These are the 59 parameters per primitive of Eq. 1 (Sec. 3.1).
+ * These are the 59 parameters per primitive of Eq. 1 (Sec. 3.1).  Planes
+ * 0..10 are stored as `dtype`, planes 11..58 as `sh_dtype`; the supported
+ * pairs are (REFINE_F32, REFINE_F32) (4-byte elements) and
+ * (REFINE_BF16, REFINE_F16) (2-byte elements: BF16 geometry and opacity, FP16
+ * colour); other pairs return REFINE_E_UNSUPPORTED.
  * n >= 0, stride >= n, n <= 2^31 - 1.  For an output scene (refine_compact)
  * n is the capacity in primitives.
  */
 typedef struct {
     int64_t n;
     int64_t stride;
-    int32_t dtype;          /* refine_dtype */
-    int32_t reserved;       /* must be 0 */
+    int32_t dtype;          /* refine_dtype of planes 0..10 */
+    int32_t sh_dtype;       /* refine_dtype of planes 11..58 */
     void* planes;           /* device */
 } refine_scene;
 
@@ -235,7 +240,7 @@ refine_status refine_select(const float* d_scores, int64_t n, double ratio, int6
  * (nullable, device int32 [out->n]) receives i_j.  out->n is the capacity:
  * survivors beyond it are not written.  d_n_out (nullable, device int64)
  * receives the number of survivors (which may exceed the capacity).
- * in and out must have the same dtype and must not overlap.
+ * in and out must have the same dtype and sh_dtype and must not overlap.
  */
 refine_status refine_compact(const refine_scene* in, const uint8_t* d_keep, const refine_scene* out,
                              int32_t* d_index_map, int64_t* d_n_out, void* d_ws, size_t ws_bytes,

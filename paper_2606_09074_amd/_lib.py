@@ -18,7 +18,7 @@ REFINE_E_UNSUPPORTED = -2
 REFINE_E_WORKSPACE = -3
 REFINE_E_HIP = -4
 
-REFINE_F32 = 0
+REFINE_F32, REFINE_BF16, REFINE_F16 = 0, 1, 2
 PROJ_COV, PROJ_DEPTH, PROJ_NONE = 0, 1, 2
 VIS_ALPHA, VIS_NONE = 0, 1
 PATH_AUTO, PATH_DIRECT, PATH_BINNED = 0, 1, 2
@@ -30,7 +30,7 @@ EXPORTED = ("refine_version", "refine_status_string", "refine_params_default", "
 
 class Scene(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("stride", ctypes.c_int64), ("dtype", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("planes", ctypes.c_void_p)]
+                ("sh_dtype", ctypes.c_int32), ("planes", ctypes.c_void_p)]
 
 
 class Params(ctypes.Structure):

@@ -3,6 +3,10 @@
 PyTorch provides device memory and the current HIP stream; every step of
 the computation runs in the library's HIP kernels.  The functions only
 check tensor shapes/dtypes/devices and pass pointers.
+
+A scene is a [59, stride] tensor: float32 for FP32 storage, or int16
+holding the raw bits of BF16 planes 0..10 and FP16 planes 11..58 (the
+mixed 2-byte storage; see synth.quantize_bf16_f16).
 """
 from __future__ import annotations
 
@@ -28,18 +32,26 @@ def _stream_ptr(stream: Optional[torch.cuda.Stream]) -> ctypes.c_void_p:
     return ctypes.c_void_p(s.cuda_stream)
 
 
+def storage_dtypes(planes: torch.Tensor) -> tuple[int, int]:
+    """(dtype, sh_dtype) of a scene tensor."""
+    if planes.dtype == torch.float32:
+        return _lib.REFINE_F32, _lib.REFINE_F32
+    if planes.dtype == torch.int16:
+        return _lib.REFINE_BF16, _lib.REFINE_F16
+    raise ValueError("scene planes must be float32, or int16 bit patterns of BF16 (planes 0..10) and FP16 (11..58)")
+
+
 def _scene(planes: torch.Tensor, n: Optional[int] = None) -> Scene:
     if planes.dim() != 2 or planes.shape[0] != 59:
         raise ValueError("scene planes must be a [59, stride] tensor")
-    if planes.dtype != torch.float32:
-        raise ValueError("scene planes must be float32")
+    dt, sh = storage_dtypes(planes)
     if not planes.is_cuda:
         raise ValueError("scene planes must live on the GPU")
     if planes.stride(1) != 1 or planes.stride(0) < planes.shape[1]:
         raise ValueError("scene planes must be row-contiguous")
     stride = planes.stride(0)
     n = planes.shape[1] if n is None else int(n)
-    return Scene(n, stride, _lib.REFINE_F32, 0, ctypes.c_void_p(planes.data_ptr()))
+    return Scene(n, stride, dt, sh, ctypes.c_void_p(planes.data_ptr()))
 
 
 def workspace_size(n: int, n_views: int) -> int:
@@ -166,7 +178,7 @@ def prune(planes: torch.Tensor, cams: torch.Tensor, ratio: float, params: Option
     keep = torch.empty(n, dtype=torch.uint8, device=dev)
     n_keep = torch.empty(1, dtype=torch.int64, device=dev)
     cap = n - prune_count(n, ratio)
-    out = torch.empty((59, max(cap, 1)), dtype=torch.float32, device=dev)
+    out = torch.empty((59, max(cap, 1)), dtype=planes.dtype, device=dev)
     idx = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
     refine_stats(planes, st, ws, params, stream=stream)
     refine_score(planes, cams, st, scores, ws, params, stream=stream)

@@ -16,16 +16,22 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 bool finite(double x) { return std::isfinite(x); }
 
-refine_status check_scene(const refine_scene* s, bool output)
+bool known_dtype(int32_t d) { return d == REFINE_F32 || d == REFINE_BF16 || d == REFINE_F16; }
+
+// Storage format of a scene (call after check_scene succeeded).
+int storage_of(const refine_scene* s) { return s->dtype == REFINE_F32 ? kStoreF32 : kStoreBF16F16; }
+
+refine_status check_scene(const refine_scene* s)
 {
     if (!s) return REFINE_E_INVALID;
     if (s->n < 0 || s->stride < 0 || s->stride < s->n) return REFINE_E_INVALID;
-    if (s->reserved != 0) return REFINE_E_INVALID;
-    if (s->dtype != REFINE_F32) return REFINE_E_UNSUPPORTED;
+    if (!known_dtype(s->dtype) || !known_dtype(s->sh_dtype)) return REFINE_E_INVALID;
+    const bool f32 = s->dtype == REFINE_F32 && s->sh_dtype == REFINE_F32;
+    const bool mixed = s->dtype == REFINE_BF16 && s->sh_dtype == REFINE_F16;
+    if (!f32 && !mixed) return REFINE_E_UNSUPPORTED;
     if (s->n > (int64_t)std::numeric_limits<int32_t>::max()) return REFINE_E_UNSUPPORTED;
     if (s->stride > std::numeric_limits<int64_t>::max() / (kPlanes * 4)) return REFINE_E_INVALID;
     if (s->n > 0 && !s->planes) return REFINE_E_INVALID;
-    (void)output;
     return REFINE_OK;
 }
 
@@ -152,14 +158,14 @@ refine_status refine_workspace_size(int64_t n, int32_t n_views, size_t* bytes)
 refine_status refine_stats(const refine_scene* scene, const refine_params* params, refine_stats_t* d_stats,
                            void* d_ws, size_t ws_bytes, void* stream)
 {
-    refine_status s = check_scene(scene, false);
+    refine_status s = check_scene(scene);
     if (s != REFINE_OK) return s;
     if ((s = check_params(params)) != REFINE_OK) return s;
     if (!d_stats) return REFINE_E_INVALID;
     Workspace ws;
     if ((s = check_workspace(scene->n, 0, false, d_ws, ws_bytes, &ws)) != REFINE_OK) return s;
-    const hipError_t e = launch_stats(static_cast<const float*>(scene->planes), scene->stride, scene->n, *params,
-                                      d_stats, ws, static_cast<hipStream_t>(stream));
+    const hipError_t e = launch_stats(scene->planes, storage_of(scene), scene->stride, scene->n, *params, d_stats,
+                                      ws, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? REFINE_OK : REFINE_E_HIP;
 }
 
@@ -168,7 +174,7 @@ namespace {
 refine_status check_score_args(const refine_scene* scene, int32_t n_views, const refine_params* params,
                                const refine_stats_t* d_stats)
 {
-    refine_status s = check_scene(scene, false);
+    refine_status s = check_scene(scene);
     if (s != REFINE_OK) return s;
     if ((s = check_params(params)) != REFINE_OK) return s;
     if (n_views < 1 || !d_stats) return REFINE_E_INVALID;
@@ -187,8 +193,8 @@ refine_status refine_score_prepare(const refine_scene* scene, const float* d_cam
     if (!d_cams) return REFINE_E_INVALID;
     Workspace ws;
     if ((s = check_workspace(scene->n, n_views, true, d_ws, ws_bytes, &ws)) != REFINE_OK) return s;
-    const hipError_t e = launch_score_prepare(static_cast<const float*>(scene->planes), scene->stride, scene->n,
-                                              d_cams, n_views, *params, d_stats, ws, static_cast<hipStream_t>(stream));
+    const hipError_t e = launch_score_prepare(scene->planes, storage_of(scene), scene->stride, scene->n, d_cams,
+                                              n_views, *params, d_stats, ws, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? REFINE_OK : REFINE_E_HIP;
 }
 
@@ -201,7 +207,7 @@ refine_status refine_score_views(const refine_scene* scene, int32_t n_views, con
     if (scene->n > 0 && !d_scores) return REFINE_E_INVALID;
     Workspace ws;
     if ((s = check_workspace(scene->n, n_views, true, d_ws, ws_bytes, &ws)) != REFINE_OK) return s;
-    const hipError_t e = launch_score_views(static_cast<const float*>(scene->planes), scene->stride, scene->n, n_views,
+    const hipError_t e = launch_score_views(scene->planes, storage_of(scene), scene->stride, scene->n, n_views,
                                             *params, d_stats, d_scores, d_evaluated, ws,
                                             static_cast<hipStream_t>(stream));
     return e == hipSuccess ? REFINE_OK : REFINE_E_HIP;
@@ -245,23 +251,24 @@ refine_status refine_select(const float* d_scores, int64_t n, double ratio, int6
 refine_status refine_compact(const refine_scene* in, const uint8_t* d_keep, const refine_scene* out,
                              int32_t* d_index_map, int64_t* d_n_out, void* d_ws, size_t ws_bytes, void* stream)
 {
-    refine_status s = check_scene(in, false);
+    refine_status s = check_scene(in);
     if (s != REFINE_OK) return s;
-    if ((s = check_scene(out, true)) != REFINE_OK) return s;
-    if (in->dtype != out->dtype) return REFINE_E_INVALID;
+    if ((s = check_scene(out)) != REFINE_OK) return s;
+    if (in->dtype != out->dtype || in->sh_dtype != out->sh_dtype) return REFINE_E_INVALID;
     if (in->n > 0 && !d_keep) return REFINE_E_INVALID;
+    const size_t es = storage_bytes(storage_of(in));
     if (in->n > 0 && out->n > 0) {
         const char* a0 = static_cast<const char*>(in->planes);
-        const char* a1 = a0 + (size_t)kPlanes * (size_t)in->stride * sizeof(float);
+        const char* a1 = a0 + (size_t)kPlanes * (size_t)in->stride * es;
         const char* b0 = static_cast<const char*>(out->planes);
-        const char* b1 = b0 + (size_t)kPlanes * (size_t)out->stride * sizeof(float);
+        const char* b1 = b0 + (size_t)kPlanes * (size_t)out->stride * es;
         if (a0 < b1 && b0 < a1) return REFINE_E_INVALID;
     }
     Workspace ws;
     if ((s = check_workspace(in->n, 0, false, d_ws, ws_bytes, &ws)) != REFINE_OK) return s;
-    const hipError_t e = launch_compact(static_cast<const float*>(in->planes), in->stride, in->n, d_keep,
-                                        static_cast<float*>(out->planes), out->stride, out->n, d_index_map, d_n_out,
-                                        ws, static_cast<hipStream_t>(stream));
+    const hipError_t e = launch_compact(in->planes, storage_of(in), in->stride, in->n, d_keep, out->planes,
+                                        out->stride, out->n, d_index_map, d_n_out, ws,
+                                        static_cast<hipStream_t>(stream));
     return e == hipSuccess ? REFINE_OK : REFINE_E_HIP;
 }
 

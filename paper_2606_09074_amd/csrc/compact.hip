@@ -8,7 +8,8 @@
 // order inside the tile is the index order, so the copy is stable) and then
 // streams all 59 planes: each row of 256 consecutive primitives is one
 // coalesced load per plane, and the survivors of a row land in one
-// contiguous output range.  Bit copies, no arithmetic on the values.
+// contiguous output range.  Bit copies of 4-byte (FP32) or 2-byte (BF16 /
+// FP16) elements, no arithmetic on the values.
 #include "refine_internal.hpp"
 
 namespace refine {
@@ -60,12 +61,13 @@ __device__ inline int64_t tile_start(const uint32_t* __restrict__ tile_cnt, cons
     return off_from_scan ? (int64_t)tile_off[blockIdx.x] : (int64_t)block_sum_prefix(tile_cnt, blockIdx.x);
 }
 
-__global__ __launch_bounds__(kBlock) void compact_scatter(const float* __restrict__ in, int64_t in_stride, int n,
+template <class E>
+__global__ __launch_bounds__(kBlock) void compact_scatter(const E* __restrict__ in, int64_t in_stride, int n,
                                                             const uint8_t* __restrict__ keep,
                                                             const uint32_t* __restrict__ tile_cnt,
                                                             const uint32_t* __restrict__ tile_off, int ntiles,
                                                             int off_from_scan, int64_t* __restrict__ d_n_out,
-                                                            float* __restrict__ out, int64_t out_stride,
+                                                            E* __restrict__ out, int64_t out_stride,
                                                             int64_t capacity, int32_t* __restrict__ index_map)
 {
     const int64_t tstart = tile_start(tile_cnt, tile_off, ntiles, off_from_scan, d_n_out);
@@ -103,9 +105,9 @@ __global__ __launch_bounds__(kBlock) void compact_scatter(const float* __restric
     }
     if (kept_bits == 0u && __ballot(kept_bits != 0u) == 0ull) return;
     for (int p = 0; p < kPlanes; ++p) {
-        const float* src = in + (int64_t)p * in_stride + base + (int)threadIdx.x;
-        float* dst = out + (int64_t)p * out_stride;
-        float v[kItems];
+        const E* src = in + (int64_t)p * in_stride + base + (int)threadIdx.x;
+        E* dst = out + (int64_t)p * out_stride;
+        E v[kItems];
 #pragma unroll
         for (int k = 0; k < kItems; ++k)
             if ((kept_bits >> k) & 1u) v[k] = src[k * kBlock];
@@ -115,40 +117,64 @@ __global__ __launch_bounds__(kBlock) void compact_scatter(const float* __restric
     }
 }
 
-// compact_scatter for 16-byte aligned planes (stride a multiple of 4) and a
-// 4-byte aligned mask.  A tile is 4 rows of 1024 primitives; each lane loads
-// 4 consecutive primitives of a row with one 16-byte load per plane.  The
-// survivors of two planes are packed in LDS at their tile-local positions
-// (per-row exclusive scans in index order: the copy stays stable), then
-// written out with contiguous, fully active 4-byte stores.
-constexpr int kVecRows = kTile / (4 * kBlock);   // 4
-constexpr int kStagePlanes = 2;
+// compact_scatter for 16-byte aligned planes (stride a multiple of 16 bytes)
+// and a 4-byte aligned mask.  A tile is rows of 16 bytes per lane: 4 rows of
+// 1024 FP32 primitives, or 2 rows of 2048 2-byte primitives; each lane loads
+// its PER consecutive primitives of a row with one 16-byte load per plane.
+// The survivors of 8 KB worth of planes are packed in LDS at their
+// tile-local positions (per-row exclusive scans in index order: the copy
+// stays stable), then written out with contiguous, fully active stores of 4
+// bytes (two 2-byte elements when `pair_store`: output 4-byte aligned with an
+// even stride).
+template <class E, int PER>
+__device__ inline void unpack16(const uint4& x, E (&v)[PER])
+{
+    const uint32_t w[4] = {x.x, x.y, x.z, x.w};
+    if constexpr (PER == 4) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[j] = w[j];
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            v[2 * j] = (E)(w[j] & 0xFFFFu);
+            v[2 * j + 1] = (E)(w[j] >> 16);
+        }
+    }
+}
 
-__global__ __launch_bounds__(kBlock) void compact_scatter_lds(const float* __restrict__ in, int64_t in_stride, int n,
+template <class E>
+__global__ __launch_bounds__(kBlock) void compact_scatter_lds(const E* __restrict__ in, int64_t in_stride, int n,
                                                                 const uint8_t* __restrict__ keep,
                                                                 const uint32_t* __restrict__ tile_cnt,
                                                                 const uint32_t* __restrict__ tile_off, int ntiles,
                                                                 int off_from_scan, int64_t* __restrict__ d_n_out,
-                                                                float* __restrict__ out, int64_t out_stride,
-                                                                int64_t capacity, int32_t* __restrict__ index_map)
+                                                                E* __restrict__ out, int64_t out_stride,
+                                                                int64_t capacity, int32_t* __restrict__ index_map,
+                                                                int pair_store)
 {
+    constexpr int PER = 16 / sizeof(E);               // primitives per lane per row
+    constexpr int ROWS = kTile / (PER * kBlock);      // 4 or 2
+    constexpr int kStagePlanes = 8 / sizeof(E);       // 32 KB of LDS
     const int64_t out0 = tile_start(tile_cnt, tile_off, ntiles, off_from_scan, d_n_out);
-    __shared__ uint32_t wtot[kVecRows][kWaves];
-    __shared__ float stage[kStagePlanes][kTile];
+    __shared__ uint32_t wtot[ROWS][kWaves];
+    __shared__ E stage[kStagePlanes][kTile];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int base = blockIdx.x * kTile;
-    uint32_t flags[kVecRows], incl[kVecRows];
+    uint32_t flags[ROWS], incl[ROWS];
 #pragma unroll
-    for (int r = 0; r < kVecRows; ++r) {
-        const int i0 = base + r * 4 * kBlock + 4 * (int)threadIdx.x;
+    for (int r = 0; r < ROWS; ++r) {
+        const int i0 = base + r * PER * kBlock + PER * (int)threadIdx.x;
         uint32_t f = 0u;
-        if (i0 + 3 < n) {
-            const uint32_t w = *reinterpret_cast<const uint32_t*>(keep + i0);
+        if (i0 + PER - 1 < n) {
 #pragma unroll
-            for (int j = 0; j < 4; ++j) f |= ((w >> (8 * j)) & 0xFFu) ? (1u << j) : 0u;
+            for (int h = 0; h < PER / 4; ++h) {
+                const uint32_t w = *reinterpret_cast<const uint32_t*>(keep + i0 + 4 * h);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) f |= ((w >> (8 * j)) & 0xFFu) ? (1u << (4 * h + j)) : 0u;
+            }
         } else {
 #pragma unroll
-            for (int j = 0; j < 4; ++j) f |= (i0 + j < n && keep[i0 + j]) ? (1u << j) : 0u;
+            for (int j = 0; j < PER; ++j) f |= (i0 + j < n && keep[i0 + j]) ? (1u << j) : 0u;
         }
         flags[r] = f;
         uint32_t c = (uint32_t)__popc(f);
@@ -162,10 +188,10 @@ __global__ __launch_bounds__(kBlock) void compact_scatter_lds(const float* __res
     }
     __syncthreads();
     // tile-local position of this lane's first survivor in each row
-    uint32_t lstart[kVecRows];
+    uint32_t lstart[ROWS];
     uint32_t row = 0;
 #pragma unroll
-    for (int r = 0; r < kVecRows; ++r) {
+    for (int r = 0; r < ROWS; ++r) {
         uint32_t before = 0, tot = 0;
 #pragma unroll
         for (int w = 0; w < kWaves; ++w) {
@@ -179,11 +205,11 @@ __global__ __launch_bounds__(kBlock) void compact_scatter_lds(const float* __res
     const int kept = (int)min((int64_t)tile_cnt[blockIdx.x], room > 0 ? room : (int64_t)0);
     if (index_map) {
 #pragma unroll
-        for (int r = 0; r < kVecRows; ++r) {
-            const int i0 = base + r * 4 * kBlock + 4 * (int)threadIdx.x;
+        for (int r = 0; r < ROWS; ++r) {
+            const int i0 = base + r * PER * kBlock + PER * (int)threadIdx.x;
             uint32_t k = 0;
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
+            for (int j = 0; j < PER; ++j)
                 if ((flags[r] >> j) & 1u) {
                     if ((int)(lstart[r] + k) < kept) index_map[out0 + lstart[r] + k] = i0 + j;
                     ++k;
@@ -191,26 +217,27 @@ __global__ __launch_bounds__(kBlock) void compact_scatter_lds(const float* __res
         }
     }
     if (kept == 0) return;   // uniform across the block
+    // elements before the first 4-byte boundary of the output range (pair stores)
+    const int lead = (sizeof(E) == 2 && pair_store) ? (int)(out0 & 1) : 0;
     for (int p0 = 0; p0 < kPlanes; p0 += kStagePlanes) {
 #pragma unroll
         for (int q = 0; q < kStagePlanes; ++q) {
             if (p0 + q >= kPlanes) break;
-            const float* src = in + (int64_t)(p0 + q) * in_stride;
+            const E* src = in + (int64_t)(p0 + q) * in_stride;
 #pragma unroll
-            for (int r = 0; r < kVecRows; ++r) {
+            for (int r = 0; r < ROWS; ++r) {
                 if (!flags[r]) continue;
-                const int i0 = base + r * 4 * kBlock + 4 * (int)threadIdx.x;
-                float v[4];
-                if (i0 + 3 < n) {
-                    const float4 x = *reinterpret_cast<const float4*>(src + i0);
-                    v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+                const int i0 = base + r * PER * kBlock + PER * (int)threadIdx.x;
+                E v[PER];
+                if (i0 + PER - 1 < n) {
+                    unpack16<E, PER>(*reinterpret_cast<const uint4*>(src + i0), v);
                 } else {
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) v[j] = (i0 + j < n) ? src[i0 + j] : 0.0f;
+                    for (int j = 0; j < PER; ++j) v[j] = (i0 + j < n) ? src[i0 + j] : E(0);
                 }
                 uint32_t k = 0;
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
+                for (int j = 0; j < PER; ++j)
                     if ((flags[r] >> j) & 1u) stage[q][lstart[r] + k++] = v[j];
             }
         }
@@ -218,16 +245,43 @@ __global__ __launch_bounds__(kBlock) void compact_scatter_lds(const float* __res
 #pragma unroll
         for (int q = 0; q < kStagePlanes; ++q) {
             if (p0 + q >= kPlanes) break;
-            float* dst = out + (int64_t)(p0 + q) * out_stride + out0;
-            for (int j = threadIdx.x; j < kept; j += kBlock) dst[j] = stage[q][j];
+            E* dst = out + (int64_t)(p0 + q) * out_stride + out0;
+            if (sizeof(E) == 2 && pair_store) {
+                if (lead && threadIdx.x == 0) dst[0] = stage[q][0];
+                const int npairs = (kept - lead) >> 1;
+                uint32_t* dst2 = reinterpret_cast<uint32_t*>(dst + lead);
+                for (int j = threadIdx.x; j < npairs; j += kBlock)
+                    dst2[j] = (uint32_t)stage[q][lead + 2 * j] | ((uint32_t)stage[q][lead + 2 * j + 1] << 16);
+                if (((kept - lead) & 1) && threadIdx.x == 0) dst[kept - 1] = stage[q][kept - 1];
+            } else {
+                for (int j = threadIdx.x; j < kept; j += kBlock) dst[j] = stage[q][j];
+            }
         }
         __syncthreads();
     }
 }
 
+template <class E>
+void launch_compact_t(const E* in, int64_t in_stride, int n, const uint8_t* d_keep, E* out, int64_t out_stride,
+                      int64_t capacity, int32_t* d_index_map, int64_t* d_n_out, const Workspace& ws, int ntiles,
+                      int from_scan, hipStream_t stream)
+{
+    const bool vec = (reinterpret_cast<uintptr_t>(in) % 16 == 0) && ((in_stride * sizeof(E)) % 16 == 0) &&
+                     (reinterpret_cast<uintptr_t>(d_keep) % 4 == 0);
+    const int pair_store = (reinterpret_cast<uintptr_t>(out) % 4 == 0) && (out_stride % 2 == 0) ? 1 : 0;
+    if (vec)
+        hipLaunchKernelGGL(compact_scatter_lds<E>, dim3(ntiles), dim3(kBlock), 0, stream, in, in_stride, n, d_keep,
+                           ws.tile_cnt, ws.tile_off, ntiles, from_scan, d_n_out, out, out_stride, capacity,
+                           d_index_map, pair_store);
+    else
+        hipLaunchKernelGGL(compact_scatter<E>, dim3(ntiles), dim3(kBlock), 0, stream, in, in_stride, n, d_keep,
+                           ws.tile_cnt, ws.tile_off, ntiles, from_scan, d_n_out, out, out_stride, capacity,
+                           d_index_map);
+}
+
 }  // namespace
 
-hipError_t launch_compact(const float* in, int64_t in_stride, int64_t n, const uint8_t* d_keep, float* out,
+hipError_t launch_compact(const void* in, int st, int64_t in_stride, int64_t n, const uint8_t* d_keep, void* out,
                           int64_t out_stride, int64_t capacity, int32_t* d_index_map, int64_t* d_n_out,
                           const Workspace& ws, hipStream_t stream)
 {
@@ -240,16 +294,12 @@ hipError_t launch_compact(const float* in, int64_t in_stride, int64_t n, const u
     const int from_scan = ntiles > kPrefixTilesMax ? 1 : 0;
     if (from_scan)
         hipLaunchKernelGGL(compact_scan, dim3(1), dim3(kScanThreads), 0, stream, ws.tile_cnt, ws.tile_off, ntiles);
-    const bool vec = (reinterpret_cast<uintptr_t>(in) % 16 == 0) && (in_stride % 4 == 0) &&
-                     (reinterpret_cast<uintptr_t>(d_keep) % 4 == 0);
-    if (vec)
-        hipLaunchKernelGGL(compact_scatter_lds, dim3(ntiles), dim3(kBlock), 0, stream, in, in_stride, (int)n, d_keep,
-                           ws.tile_cnt, ws.tile_off, ntiles, from_scan, d_n_out, out, out_stride, capacity,
-                           d_index_map);
+    if (storage_bytes(st) == 4)
+        launch_compact_t(static_cast<const uint32_t*>(in), in_stride, (int)n, d_keep, static_cast<uint32_t*>(out),
+                         out_stride, capacity, d_index_map, d_n_out, ws, ntiles, from_scan, stream);
     else
-        hipLaunchKernelGGL(compact_scatter, dim3(ntiles), dim3(kBlock), 0, stream, in, in_stride, (int)n, d_keep,
-                           ws.tile_cnt, ws.tile_off, ntiles, from_scan, d_n_out, out, out_stride, capacity,
-                           d_index_map);
+        launch_compact_t(static_cast<const uint16_t*>(in), in_stride, (int)n, d_keep, static_cast<uint16_t*>(out),
+                         out_stride, capacity, d_index_map, d_n_out, ws, ntiles, from_scan, stream);
     return hipGetLastError();
 }
 

@@ -12,6 +12,15 @@ namespace refine {
 
 constexpr int kPlanes = 59;
 constexpr int kScorePlanes = 14;   // centre, log-scale, quaternion, opacity, SH DC
+constexpr int kGeomPlanes = 11;    // planes stored in the scene's dtype; the rest in its sh_dtype
+
+// Supported scene storage formats (dtype of planes 0..10, dtype of 11..58).
+enum Storage : int {
+    kStoreF32 = 0,       // FP32, FP32
+    kStoreBF16F16 = 1    // BF16, FP16
+};
+
+inline size_t storage_bytes(int st) { return st == kStoreF32 ? 4 : 2; }
 constexpr int kCamFields = 18;
 constexpr int kBlock = 256;        // threads per block of the tile kernels (4 wave64)
 constexpr int kWaves = kBlock / 64;
@@ -101,19 +110,20 @@ inline int64_t num_tiles(int64_t n) { return (n + kTile - 1) / kTile; }
 size_t workspace_layout(int64_t n, int32_t n_views, bool score, void* base, Workspace* ws);
 
 // Launchers (validated arguments; return the hipGetLastError of the launch).
-hipError_t launch_stats(const float* planes, int64_t stride, int64_t n, const refine_params& prm,
+// `st` is the scene's Storage.
+hipError_t launch_stats(const void* planes, int st, int64_t stride, int64_t n, const refine_params& prm,
                         refine_stats_t* d_stats, const Workspace& ws, hipStream_t stream);
-hipError_t launch_score_prepare(const float* planes, int64_t stride, int64_t n, const float* d_cams,
+hipError_t launch_score_prepare(const void* planes, int st, int64_t stride, int64_t n, const float* d_cams,
                                 int32_t n_views, const refine_params& prm, const refine_stats_t* d_stats,
                                 const Workspace& ws, hipStream_t stream);
-hipError_t launch_score_views(const float* planes, int64_t stride, int64_t n, int32_t n_views,
+hipError_t launch_score_views(const void* planes, int st, int64_t stride, int64_t n, int32_t n_views,
                               const refine_params& prm, const refine_stats_t* d_stats, float* d_scores,
                               int64_t* d_evaluated, const Workspace& ws, hipStream_t stream);
 hipError_t launch_select(const float* d_scores, int64_t n, int64_t n_prune, uint8_t* d_keep,
                          int64_t* d_n_keep, uint32_t* d_threshold, const Workspace& ws,
                          hipStream_t stream);
-hipError_t launch_compact(const float* in, int64_t in_stride, int64_t n, const uint8_t* d_keep,
-                          float* out, int64_t out_stride, int64_t capacity, int32_t* d_index_map,
+hipError_t launch_compact(const void* in, int st, int64_t in_stride, int64_t n, const uint8_t* d_keep,
+                          void* out, int64_t out_stride, int64_t capacity, int32_t* d_index_map,
                           int64_t* d_n_out, const Workspace& ws, hipStream_t stream);
 
 // ------------------------------------------------------------ device helpers
@@ -146,6 +156,21 @@ __device__ inline uint32_t wave_sum_u32(uint32_t v)
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
+}
+
+// Plane p of primitive i as FP32.  BF16 widens exactly (its bits are the
+// high half of an FP32), FP16 converts exactly (every half is a float).
+template <int ST>
+__device__ __forceinline__ float load_plane(const void* __restrict__ planes, int64_t stride, int p, int64_t i)
+{
+    const int64_t at = (int64_t)p * stride + i;
+    if constexpr (ST == kStoreF32) {
+        return static_cast<const float*>(planes)[at];
+    } else {
+        const uint16_t b = static_cast<const uint16_t*>(planes)[at];
+        if (p < kGeomPlanes) return __uint_as_float((uint32_t)b << 16);
+        return (float)__builtin_bit_cast(_Float16, b);
+    }
 }
 
 // Number of set bits of a wave ballot below this lane.

@@ -42,6 +42,8 @@
 // footprint any of its primitives can have, r <= 3 s_max |J|_F (the clamp
 // bounds |J|_F z by kv), inflated by a 1% margin: every skipped pair would
 // have added exactly +0, so both paths give bit-identical scores.
+#include <type_traits>
+
 #include "refine_internal.hpp"
 
 namespace refine {
@@ -136,12 +138,13 @@ constexpr int kStageVec = 5;   // float4s staged per view
 static_assert(offsetof(CamRec, ly) + sizeof(float) <= kStageVec * sizeof(float4), "staged camera fields");
 
 // Activation (Sec. 3.1 readings) of primitive i; pre is the epilogue factor.
-__device__ inline void activate(const float* __restrict__ planes, int64_t stride, int i, Prim& p, float& pre,
+template <int ST>
+__device__ inline void activate(const void* __restrict__ planes, int64_t stride, int i, Prim& p, float& pre,
                                 float& smax, const refine_stats_t* __restrict__ st, int proj, int vis_alpha, int nv)
 {
     float a[kScorePlanes];
 #pragma unroll
-    for (int k = 0; k < kScorePlanes; ++k) a[k] = planes[(int64_t)k * stride + i];
+    for (int k = 0; k < kScorePlanes; ++k) a[k] = load_plane<ST>(planes, stride, k, i);
     p.mx = a[0];
     p.my = a[1];
     p.mz = a[2];
@@ -223,8 +226,8 @@ __device__ __forceinline__ void eval_pair(const Cam& c, Prim& p, float eta, floa
     p.S += g ? P : 0.0f;
 }
 
-template <int PROJ>
-__global__ __launch_bounds__(kBlock) void score_direct(const float* __restrict__ planes, int64_t stride, int n,
+template <int PROJ, int ST>
+__global__ __launch_bounds__(kBlock) void score_direct(const void* __restrict__ planes, int64_t stride, int n,
                                                          const CamRec* __restrict__ cams, int nv,
                                                          const refine_stats_t* __restrict__ st, float eta,
                                                          float z_near, int vis_alpha, float* __restrict__ out)
@@ -233,7 +236,7 @@ __global__ __launch_bounds__(kBlock) void score_direct(const float* __restrict__
     if (i >= n) return;
     Prim p;
     float pre, smax;
-    activate(planes, stride, i, p, pre, smax, st, PROJ, vis_alpha, nv);
+    activate<ST>(planes, stride, i, p, pre, smax, st, PROJ, vis_alpha, nv);
     for (int v = 0; v < nv; ++v) eval_pair<PROJ>(cams[v], p, eta, z_near);
     out[i] = pre * p.S;
 }
@@ -271,8 +274,18 @@ __device__ inline uint32_t cell_of(float x, float y, float z, const refine_stats
 // their number, not the LDS work, sets the cost.
 constexpr int kCellsPerThread = kCells / kBlock;   // 16
 
+// Morton cell of primitive i's centre.
+template <int ST>
+__device__ inline uint32_t cell_of_prim(const void* __restrict__ planes, int64_t stride, int i,
+                                        const refine_stats_t* __restrict__ st)
+{
+    return cell_of(load_plane<ST>(planes, stride, 0, i), load_plane<ST>(planes, stride, 1, i),
+                   load_plane<ST>(planes, stride, 2, i), st);
+}
+
 // Cell histogram of the tile's primitives.
-__global__ __launch_bounds__(kBlock) void bin_hist(const float* __restrict__ planes, int64_t stride, int n,
+template <int ST>
+__global__ __launch_bounds__(kBlock) void bin_hist(const void* __restrict__ planes, int64_t stride, int n,
                                                      const refine_stats_t* __restrict__ st,
                                                      uint32_t* __restrict__ cnt)
 {
@@ -283,7 +296,7 @@ __global__ __launch_bounds__(kBlock) void bin_hist(const float* __restrict__ pla
 #pragma unroll 4
     for (int k = 0; k < kItems; ++k) {
         const int i = base + k * kBlock + (int)threadIdx.x;
-        if (i < n) atomicAdd(&h[cell_of(planes[i], planes[stride + i], planes[2 * stride + i], st)], 1u);
+        if (i < n) atomicAdd(&h[cell_of_prim<ST>(planes, stride, i, st)], 1u);
     }
     __syncthreads();
 #pragma unroll
@@ -301,7 +314,8 @@ __global__ __launch_bounds__(kScanThreads) void bin_scan(const uint32_t* __restr
 
 // Counting-sort ranks: each tile reserves one output range per occupied cell
 // with a single global atomic; its primitives take consecutive slots in it.
-__global__ __launch_bounds__(kBlock) void bin_rank(const float* __restrict__ planes, int64_t stride, int n,
+template <int ST>
+__global__ __launch_bounds__(kBlock) void bin_rank(const void* __restrict__ planes, int64_t stride, int n,
                                                      const refine_stats_t* __restrict__ st, uint32_t* __restrict__ cur,
                                                      uint32_t* __restrict__ dest)
 {
@@ -316,7 +330,7 @@ __global__ __launch_bounds__(kBlock) void bin_rank(const float* __restrict__ pla
         cell[k] = 0u;
         rank[k] = 0u;
         if (i < n) {
-            cell[k] = cell_of(planes[i], planes[stride + i], planes[2 * stride + i], st);
+            cell[k] = cell_of_prim<ST>(planes, stride, i, st);
             rank[k] = atomicAdd(&h[cell[k]], 1u);
         }
     }
@@ -340,8 +354,8 @@ __global__ __launch_bounds__(kBlock) void bin_rank(const float* __restrict__ pla
 }
 
 // Activated primitives written as records at their binned positions.
-template <int PROJ>
-__global__ __launch_bounds__(kBlock) void bin_scatter(const float* __restrict__ planes, int64_t stride, int n,
+template <int PROJ, int ST>
+__global__ __launch_bounds__(kBlock) void bin_scatter(const void* __restrict__ planes, int64_t stride, int n,
                                                         const refine_stats_t* __restrict__ st, int vis_alpha, int nv,
                                                         const uint32_t* __restrict__ dest, PrimRec* __restrict__ recs)
 {
@@ -349,7 +363,7 @@ __global__ __launch_bounds__(kBlock) void bin_scatter(const float* __restrict__ 
     if (i >= n) return;
     Prim p;
     float pre, smax;
-    activate(planes, stride, i, p, pre, smax, st, PROJ, vis_alpha, nv);
+    activate<ST>(planes, stride, i, p, pre, smax, st, PROJ, vis_alpha, nv);
     const uint32_t pos = dest[i];
     PrimRec r;
     r.mu[0] = p.mx; r.mu[1] = p.my; r.mu[2] = p.mz;
@@ -513,22 +527,23 @@ __global__ void counter_store(const unsigned long long* c, int64_t* out, int64_t
     *out = direct_pairs >= 0 ? direct_pairs : (int64_t)t;
 }
 
-template <int PROJ>
-void prepare_mode(const float* planes, int64_t stride, int n, const refine_params& prm, const refine_stats_t* d_stats,
+template <int PROJ, int ST>
+void prepare_mode(const void* planes, int64_t stride, int n, const refine_params& prm, const refine_stats_t* d_stats,
                   const Workspace& ws, int nv, hipStream_t stream)
 {
     const int vis = prm.vis_mode == REFINE_VIS_ALPHA ? 1 : 0;
     const dim3 grid((unsigned)((n + kBlock - 1) / kBlock));
     const dim3 tiles((unsigned)num_tiles(n));
-    hipLaunchKernelGGL(bin_hist, tiles, dim3(kBlock), 0, stream, planes, stride, n, d_stats, ws.cell_cnt);
+    hipLaunchKernelGGL(bin_hist<ST>, tiles, dim3(kBlock), 0, stream, planes, stride, n, d_stats, ws.cell_cnt);
     hipLaunchKernelGGL(bin_scan, dim3(1), dim3(kScanThreads), 0, stream, ws.cell_cnt, ws.cell_cur);
-    hipLaunchKernelGGL(bin_rank, tiles, dim3(kBlock), 0, stream, planes, stride, n, d_stats, ws.cell_cur, ws.dest);
-    hipLaunchKernelGGL((bin_scatter<PROJ>), grid, dim3(kBlock), 0, stream, planes, stride, n, d_stats, vis, nv, ws.dest,
+    hipLaunchKernelGGL(bin_rank<ST>, tiles, dim3(kBlock), 0, stream, planes, stride, n, d_stats, ws.cell_cur,
+                       ws.dest);
+    hipLaunchKernelGGL((bin_scatter<PROJ, ST>), grid, dim3(kBlock), 0, stream, planes, stride, n, d_stats, vis, nv, ws.dest,
                        ws.recs);
 }
 
-template <int PROJ>
-void views_mode(const float* planes, int64_t stride, int n, const refine_params& prm, const refine_stats_t* d_stats,
+template <int PROJ, int ST>
+void views_mode(const void* planes, int64_t stride, int n, const refine_params& prm, const refine_stats_t* d_stats,
                 float* d_scores, unsigned long long* evaluated, const Workspace& ws, int nv, bool binned,
                 hipStream_t stream)
 {
@@ -540,7 +555,7 @@ void views_mode(const float* planes, int64_t stride, int n, const refine_params&
                                                                              (kBlock * kBinnedPPL))),
                            dim3(kBlock), 0, stream, ws.recs, n, ws.cams, ws.culls, nv, eta, zn, d_scores, evaluated);
     else
-        hipLaunchKernelGGL((score_direct<PROJ>), grid, dim3(kBlock), 0, stream, planes, stride, n, ws.cams, nv, d_stats,
+        hipLaunchKernelGGL((score_direct<PROJ, ST>), grid, dim3(kBlock), 0, stream, planes, stride, n, ws.cams, nv, d_stats,
                            eta, zn, vis, d_scores);
 }
 
@@ -556,9 +571,26 @@ bool binned_path(const refine_params& prm, int64_t n)
 
 }  // namespace
 
-hipError_t launch_score_prepare(const float* planes, int64_t stride, int64_t n, const float* d_cams, int32_t n_views,
-                                const refine_params& prm, const refine_stats_t* d_stats, const Workspace& ws,
-                                hipStream_t stream)
+// Calls f with the compile-time projection mode and storage format.
+template <class F>
+void dispatch_mode(int proj, int st, F&& f)
+{
+    auto by_storage = [&](auto proj_c) {
+        if (st == kStoreF32)
+            f(proj_c, std::integral_constant<int, kStoreF32>{});
+        else
+            f(proj_c, std::integral_constant<int, kStoreBF16F16>{});
+    };
+    switch (proj) {
+    case REFINE_PROJ_COV: by_storage(std::integral_constant<int, REFINE_PROJ_COV>{}); break;
+    case REFINE_PROJ_DEPTH: by_storage(std::integral_constant<int, REFINE_PROJ_DEPTH>{}); break;
+    default: by_storage(std::integral_constant<int, REFINE_PROJ_NONE>{}); break;
+    }
+}
+
+hipError_t launch_score_prepare(const void* planes, int st, int64_t stride, int64_t n, const float* d_cams,
+                                int32_t n_views, const refine_params& prm, const refine_stats_t* d_stats,
+                                const Workspace& ws, hipStream_t stream)
 {
     const int nv = views_of(prm, n_views);
     const bool binned = n > 0 && binned_path(prm, n);
@@ -566,15 +598,14 @@ hipError_t launch_score_prepare(const float* planes, int64_t stride, int64_t n, 
     hipLaunchKernelGGL(camera_prep, dim3((threads + kBlock - 1) / kBlock), dim3(kBlock), 0, stream, d_cams, n_views, nv,
                        (float)prm.clamp_k, ws.cams, ws.culls, binned ? ws.cell_cnt : nullptr);
     if (!binned) return hipGetLastError();
-    switch (prm.proj_mode) {
-    case REFINE_PROJ_COV: prepare_mode<REFINE_PROJ_COV>(planes, stride, (int)n, prm, d_stats, ws, nv, stream); break;
-    case REFINE_PROJ_DEPTH: prepare_mode<REFINE_PROJ_DEPTH>(planes, stride, (int)n, prm, d_stats, ws, nv, stream); break;
-    default: prepare_mode<REFINE_PROJ_NONE>(planes, stride, (int)n, prm, d_stats, ws, nv, stream); break;
-    }
+    dispatch_mode(prm.proj_mode, st, [&](auto proj_c, auto st_c) {
+        prepare_mode<decltype(proj_c)::value, decltype(st_c)::value>(planes, stride, (int)n, prm, d_stats, ws, nv,
+                                                                     stream);
+    });
     return hipGetLastError();
 }
 
-hipError_t launch_score_views(const float* planes, int64_t stride, int64_t n, int32_t n_views,
+hipError_t launch_score_views(const void* planes, int st, int64_t stride, int64_t n, int32_t n_views,
                               const refine_params& prm, const refine_stats_t* d_stats, float* d_scores,
                               int64_t* d_evaluated, const Workspace& ws, hipStream_t stream)
 {
@@ -582,20 +613,11 @@ hipError_t launch_score_views(const float* planes, int64_t stride, int64_t n, in
     const bool binned = binned_path(prm, n);
     unsigned long long* counter = (d_evaluated && binned) ? ws.evaluated : nullptr;
     if (counter) hipLaunchKernelGGL(counter_reset, dim3(1), dim3(kEvalSlots), 0, stream, counter);
-    if (n > 0) {
-        switch (prm.proj_mode) {
-        case REFINE_PROJ_COV:
-            views_mode<REFINE_PROJ_COV>(planes, stride, (int)n, prm, d_stats, d_scores, counter, ws, nv, binned, stream);
-            break;
-        case REFINE_PROJ_DEPTH:
-            views_mode<REFINE_PROJ_DEPTH>(planes, stride, (int)n, prm, d_stats, d_scores, counter, ws, nv, binned,
-                                          stream);
-            break;
-        default:
-            views_mode<REFINE_PROJ_NONE>(planes, stride, (int)n, prm, d_stats, d_scores, counter, ws, nv, binned, stream);
-            break;
-        }
-    }
+    if (n > 0)
+        dispatch_mode(prm.proj_mode, st, [&](auto proj_c, auto st_c) {
+            views_mode<decltype(proj_c)::value, decltype(st_c)::value>(planes, stride, (int)n, prm, d_stats, d_scores,
+                                                                       counter, ws, nv, binned, stream);
+        });
     if (d_evaluated)
         hipLaunchKernelGGL(counter_store, dim3(1), dim3(1), 0, stream, ws.evaluated, d_evaluated,
                            binned ? (int64_t)-1 : n * (int64_t)nv);

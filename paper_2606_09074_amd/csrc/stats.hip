@@ -15,8 +15,8 @@
 // spatial binning quantises centres inside it.
 //
 // HBM traffic: 14 planes x 4 B = 56 B per primitive read (the 28 B of the
-// feature planes plus the non-finite check of the rest), 64 B per tile
-// written.
+// feature planes plus the non-finite check of the rest; half of that for
+// BF16/FP16 storage), 64 B per tile written.
 #include "refine_internal.hpp"
 
 namespace refine {
@@ -27,7 +27,8 @@ constexpr float kShC0 = 0.28209479177387814f;   // real SH band-0 basis value 1/
 
 __device__ inline bool finite_bits(float f) { return (__float_as_uint(f) & 0x7f800000u) != 0x7f800000u; }
 
-__global__ __launch_bounds__(kBlock) void stats_partial(const float* __restrict__ planes, int64_t stride,
+template <int ST>
+__global__ __launch_bounds__(kBlock) void stats_partial(const void* __restrict__ planes, int64_t stride,
                                                           int n, float eta, double* __restrict__ part)
 {
     const int tile = blockIdx.x;
@@ -41,7 +42,7 @@ __global__ __launch_bounds__(kBlock) void stats_partial(const float* __restrict_
         if (i >= n) break;
         float v[kScorePlanes];
 #pragma unroll
-        for (int p = 0; p < kScorePlanes; ++p) v[p] = planes[(int64_t)p * stride + i];
+        for (int p = 0; p < kScorePlanes; ++p) v[p] = load_plane<ST>(planes, stride, p, i);
         bool ok = true;
 #pragma unroll
         for (int p = 0; p < kScorePlanes; ++p) ok = ok && finite_bits(v[p]);
@@ -192,13 +193,18 @@ __global__ __launch_bounds__(kBlock) void stats_finalize(const double* __restric
 
 }  // namespace
 
-hipError_t launch_stats(const float* planes, int64_t stride, int64_t n, const refine_params& prm,
+hipError_t launch_stats(const void* planes, int st, int64_t stride, int64_t n, const refine_params& prm,
                         refine_stats_t* d_stats, const Workspace& ws, hipStream_t stream)
 {
     const int ntiles = (int)num_tiles(n);
-    if (ntiles > 0)
-        hipLaunchKernelGGL(stats_partial, dim3(ntiles), dim3(kBlock), 0, stream, planes, stride, (int)n,
-                           (float)prm.eta, ws.stat_part);
+    if (ntiles > 0) {
+        if (st == kStoreF32)
+            hipLaunchKernelGGL(stats_partial<kStoreF32>, dim3(ntiles), dim3(kBlock), 0, stream, planes, stride,
+                               (int)n, (float)prm.eta, ws.stat_part);
+        else
+            hipLaunchKernelGGL(stats_partial<kStoreBF16F16>, dim3(ntiles), dim3(kBlock), 0, stream, planes, stride,
+                               (int)n, (float)prm.eta, ws.stat_part);
+    }
     hipLaunchKernelGGL(stats_finalize, dim3(1), dim3(kBlock), 0, stream, ws.stat_part, ntiles, n, prm, d_stats);
     return hipGetLastError();
 }

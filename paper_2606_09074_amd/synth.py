@@ -196,3 +196,46 @@ def make_cameras(spec: SceneSpec, rng=None) -> np.ndarray:
         return np.zeros((0, CAM_FIELDS), dtype=np.float32)
     return np.stack(rows).astype(np.float32)
 
+
+
+# ------------------------------------------------------------ 2-byte storage
+#
+# The mixed 2-byte scene format: planes 0..10 (centre, log-scale, quaternion,
+# opacity) as bfloat16 and planes 11..58 (SH coefficients) as IEEE half, held
+# as int16 bit patterns in the same [59][stride] layout.  Conversion from
+# float32 rounds to nearest, ties to even, on the host.
+
+N_GEOM_PLANES = 11
+
+
+def f32_to_bf16_bits(x: np.ndarray) -> np.ndarray:
+    """float32 -> bfloat16 bit patterns (uint16), round to nearest even; NaN
+    stays a quiet NaN of the same sign, overflow rounds to infinity."""
+    u = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32)
+    rounded = (u.astype(np.uint64) + 0x7FFF + ((u >> 16) & 1)) >> 16
+    out = rounded.astype(np.uint16)
+    nan = np.isnan(np.asarray(x, dtype=np.float32))
+    out[nan] = ((u[nan] >> 16) | 0x0040).astype(np.uint16)
+    return out
+
+
+def bf16_bits_to_f32(b: np.ndarray) -> np.ndarray:
+    return (np.asarray(b, dtype=np.uint16).astype(np.uint32) << 16).view(np.float32)
+
+
+def quantize_bf16_f16(planes: np.ndarray) -> np.ndarray:
+    """float32 planes [59][stride] -> int16 bit patterns of the mixed format."""
+    planes = np.asarray(planes, dtype=np.float32)
+    out = np.empty(planes.shape, dtype=np.uint16)
+    out[:N_GEOM_PLANES] = f32_to_bf16_bits(planes[:N_GEOM_PLANES])
+    out[N_GEOM_PLANES:] = planes[N_GEOM_PLANES:].astype(np.float16).view(np.uint16)
+    return out.view(np.int16)
+
+
+def dequantize_bf16_f16(bits: np.ndarray) -> np.ndarray:
+    """int16 bit patterns of the mixed format -> float32 (exact)."""
+    u = np.asarray(bits).view(np.uint16)
+    out = np.empty(u.shape, dtype=np.float32)
+    out[:N_GEOM_PLANES] = bf16_bits_to_f32(u[:N_GEOM_PLANES])
+    out[N_GEOM_PLANES:] = u[N_GEOM_PLANES:].view(np.float16).astype(np.float32)
+    return out

@@ -61,7 +61,8 @@ def run_gpu(planes: np.ndarray, cams: np.ndarray, n: int | None = None, ratio: f
                           n_keep_out=nk, threshold_out=thr, n=n)
         k = int(nk.item())
         cap = max(k, 0)
-        out = torch.full((59, max(cap, 1) + 3), float("nan"), dtype=torch.float32, device=dev)
+        fill = float("nan") if pl.dtype == torch.float32 else INT16_FILL
+        out = torch.full((59, max(cap, 1) + 3), fill, dtype=pl.dtype, device=dev)
         idx = torch.full((max(cap, 1) + 3,), -7, dtype=torch.int32, device=dev)
         nout = torch.full((1,), -1, dtype=torch.int64, device=dev)
         api.refine_compact(pl, keep, out, ws, index_map_out=idx, n_out=nout, n=n, capacity=cap)
@@ -74,6 +75,44 @@ def run_gpu(planes: np.ndarray, cams: np.ndarray, n: int | None = None, ratio: f
         res["n_out"] = int(nout.item())
         res["capacity"] = cap
     return res
+
+
+# what run_gpu pre-fills an int16 compaction output with (float32: NaN)
+INT16_FILL = -12345
+
+
+def oracle_all(planes, cams, n=None, **kw):
+    """Stats, lambda and scores (with ambiguity intervals) from the oracle."""
+    import oracle
+    prm = oracle_params(**kw)
+    F = oracle.stats(planes, n=n, eta=prm.eta)
+    lam = oracle.lam(F, prm)
+    D, lo, hi, na = oracle.score(planes, cams, lam, prm, n=n)
+    return F, lam, D, lo, hi
+
+
+STATS_RTOL = 1e-6
+
+
+def check_stats(gs, F, lam, what):
+    for k in ("ybar", "f_col", "f_opa", "f_gem"):
+        assert abs(gs[k] - F[k]) <= STATS_RTOL * abs(F[k]) + 1e-15, (what, k, gs[k], F[k])
+    np.testing.assert_allclose(gs["lambda"], lam, rtol=STATS_RTOL, atol=1e-12)
+
+
+def check_compact(planes, n, r):
+    """Survivors bit-exact in the storage type, index map exact, nothing
+    written beyond n_keep."""
+    keep = r["keep"].astype(bool)
+    k = int(keep.sum())
+    assert r["n_keep"] == k and r["n_out"] == k
+    bits = np.uint32 if planes.dtype.itemsize == 4 else np.uint16
+    ref = planes[:, :n][:, keep]
+    np.testing.assert_array_equal(r["out"][:, :k].view(bits), ref.view(bits))
+    np.testing.assert_array_equal(r["index_map"][:k], np.nonzero(keep)[0].astype(np.int32))
+    tail = r["out"][:, k:]
+    assert (np.all(np.isnan(tail)) if planes.dtype == np.float32 else np.all(tail == INT16_FILL))
+    assert np.all(r["index_map"][k:] == -7)
 
 
 def float_keys(x: np.ndarray) -> np.ndarray:

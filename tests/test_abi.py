@@ -83,9 +83,9 @@ def test_workspace_size(lib):
 FAKE = 0x10000   # never dereferenced: every call below fails validation first
 
 
-def _scene(n=100, stride=None, dtype=0, reserved=0, planes=FAKE):
+def _scene(n=100, stride=None, dtype=0, sh_dtype=0, planes=FAKE):
     from paper_2606_09074_amd import _lib
-    return _lib.Scene(n, n if stride is None else stride, dtype, reserved, ctypes.c_void_p(planes))
+    return _lib.Scene(n, n if stride is None else stride, dtype, sh_dtype, ctypes.c_void_p(planes))
 
 
 def test_stats_validation(lib):
@@ -99,9 +99,14 @@ def test_stats_validation(lib):
     assert call(None) == E
     assert call(_scene(n=-1)) == E
     assert call(_scene(n=10, stride=5)) == E
-    assert call(_scene(reserved=1)) == E
     assert call(_scene(planes=0)) == E
-    assert call(_scene(dtype=7)) == _lib.REFINE_E_UNSUPPORTED
+    # storage pairs: unknown dtypes are invalid, known but unsupported pairs unsupported
+    assert call(_scene(dtype=7)) == E
+    assert call(_scene(sh_dtype=-1)) == E
+    U = _lib.REFINE_E_UNSUPPORTED
+    F32, BF16, F16 = _lib.REFINE_F32, _lib.REFINE_BF16, _lib.REFINE_F16
+    for dt, sh in ((F32, BF16), (F32, F16), (BF16, F32), (BF16, BF16), (F16, F16), (F16, BF16)):
+        assert call(_scene(dtype=dt, sh_dtype=sh)) == U, (dt, sh)
     assert call(_scene(n=1 << 31)) == _lib.REFINE_E_UNSUPPORTED
     assert call(_scene(), prm=None) == E
     assert call(_scene(), out=None) == E
@@ -172,6 +177,12 @@ def test_compact_validation(lib):
         return lib.refine_compact(ctypes.byref(src), keep, ctypes.byref(dst), None, None, ws, wsb, None)
     assert call(keep=None) == E
     assert call(dst=_scene(n=50, planes=FAKE + 64)) == E                 # overlapping buffers
-    assert call(dst=_scene(n=50, dtype=7, planes=0x4000000)) == _lib.REFINE_E_UNSUPPORTED
+    assert call(dst=_scene(n=50, dtype=7, planes=0x4000000)) == E
+    # in and out must share the storage pair
+    mixed = dict(dtype=_lib.REFINE_BF16, sh_dtype=_lib.REFINE_F16)
+    assert call(dst=_scene(n=50, planes=0x4000000, **mixed)) == E
+    assert call(src=_scene(n=100, **mixed)) == E
+    # 2-byte scenes: 59 planes x 100 x 2 B = 11800 B, so an output 2 B before the end overlaps
+    assert call(src=_scene(n=100, **mixed), dst=_scene(n=50, planes=FAKE + 11798, **mixed)) == E
     assert call(dst=_scene(n=50, stride=10, planes=0x4000000)) == E
     assert call(wsb=8) == _lib.REFINE_E_WORKSPACE

@@ -11,14 +11,12 @@ FP32 terms, FP64 sums).
 import numpy as np
 import pytest
 
-from tests.gpu_common import (check_mask_vs_oracle, check_scores, expected_keep_from_scores, gpu_params, log,
-                              oracle_params, run_gpu, workload)
+from tests.gpu_common import (check_compact, check_mask_vs_oracle, check_scores, check_stats,
+                              expected_keep_from_scores, gpu_params, log, oracle_all, oracle_params, run_gpu,
+                              workload)
 from tests.helpers import camera, planes_from_prims, raw_prim
 
 pytestmark = pytest.mark.gpu
-
-STATS_RTOL = 1e-6
-
 
 @pytest.fixture(scope="module", autouse=True)
 def _gpu():
@@ -26,21 +24,6 @@ def _gpu():
     assert torch.cuda.is_available(), "GPU tests need a GPU"
     from paper_2606_09074_amd import _lib
     _lib.load()
-
-
-def oracle_all(planes, cams, n=None, **kw):
-    import oracle
-    prm = oracle_params(**kw)
-    F = oracle.stats(planes, n=n, eta=prm.eta)
-    lam = oracle.lam(F, prm)
-    D, lo, hi, na = oracle.score(planes, cams, lam, prm, n=n)
-    return F, lam, D, lo, hi
-
-
-def check_stats(gs, F, lam, what):
-    for k in ("ybar", "f_col", "f_opa", "f_gem"):
-        assert abs(gs[k] - F[k]) <= STATS_RTOL * abs(F[k]) + 1e-15, (what, k, gs[k], F[k])
-    np.testing.assert_allclose(gs["lambda"], lam, rtol=STATS_RTOL, atol=1e-12)
 
 
 def test_small_workload_full_pipeline():
@@ -55,18 +38,7 @@ def test_small_workload_full_pipeline():
     check_scores(r["scores"], D, lo, hi, "small scores")
     np.testing.assert_array_equal(r["keep"], expected_keep_from_scores(r["scores"], n_prune))
     check_mask_vs_oracle(r["keep"], D, lo, hi, n_prune, "small mask")
-    _check_compact(planes, spec.n, r)
-
-
-def _check_compact(planes, n, r):
-    keep = r["keep"].astype(bool)
-    k = int(keep.sum())
-    assert r["n_keep"] == k and r["n_out"] == k
-    ref = planes[:, :n][:, keep]
-    np.testing.assert_array_equal(r["out"][:, :k].view(np.uint32), ref.view(np.uint32))
-    np.testing.assert_array_equal(r["index_map"][:k], np.nonzero(keep)[0].astype(np.int32))
-    # nothing beyond the capacity was written
-    assert np.all(np.isnan(r["out"][:, k:])) and np.all(r["index_map"][k:] == -7)
+    check_compact(planes, spec.n, r)
 
 
 @pytest.mark.parametrize("n", [1, 63, 64, 65, 255, 256, 257, 4095, 4096, 4097, 9000])
@@ -80,7 +52,7 @@ def test_ragged_sizes(n):
     import oracle
     n_prune = oracle.n_prune(n, 0.5)
     np.testing.assert_array_equal(r["keep"], expected_keep_from_scores(r["scores"], n_prune))
-    _check_compact(sub, n, r)
+    check_compact(sub, n, r)
 
 
 def test_padded_stride():
@@ -94,7 +66,7 @@ def test_padded_stride():
     check_stats(r["stats"], F, lam, "padded")
     assert r["stats"]["n_nonfinite"] == 0
     check_scores(r["scores"], D, lo, hi, "padded")
-    _check_compact(planes, 5000, r)
+    check_compact(planes, 5000, r)
 
 
 def test_empty_scene():
@@ -251,7 +223,7 @@ def test_medium_workload_full_parity(ratio):
     check_scores(r["scores"], D, lo, hi, "medium scores")
     np.testing.assert_array_equal(r["keep"], expected_keep_from_scores(r["scores"], n_prune))
     check_mask_vs_oracle(r["keep"], D, lo, hi, n_prune, f"medium mask beta={ratio}")
-    _check_compact(planes, spec.n, r)
+    check_compact(planes, spec.n, r)
 
 
 _ORACLE_CACHE = {}
@@ -274,7 +246,7 @@ def test_large_workload_sampled_parity():
     check_stats(r["stats"], F, lam, "large")
     check_scores(r["scores"][idx], D, lo, hi, "large sampled scores")
     np.testing.assert_array_equal(r["keep"], expected_keep_from_scores(r["scores"], n_prune))
-    _check_compact(planes, spec.n, r)
+    check_compact(planes, spec.n, r)
 
 
 def _paths(planes, cams, n=None, **kw):
