@@ -87,6 +87,10 @@ def main() -> int:
     ap.add_argument("--storage", default="f32", choices=["f32", "bf16-f16"],
                     help="scene storage: FP32 planes, or BF16 geometry/opacity + FP16 SH (arithmetic is FP32 either way)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-jobs", type=int, default=240,
+                    help="prune jobs per storage format in the served-latency run (0: skip it)")
+    ap.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrival rate of the served jobs (1/s)")
+    ap.add_argument("--serve-slots", type=int, default=4, help="jobs in flight at once (one HIP stream each)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (3 times) and exit: the reference "
                          "kernel for scaling HBM traffic counters")
@@ -226,6 +230,8 @@ def main() -> int:
                "sample": f"full {spec.name} prune (stats+score+select+compact), {tc:.2f} s",
                "ms_per_prune": round(tc * 1e3, 1)}
 
+    serving = serve_bench(args) if args.serve_jobs > 0 else None
+
     line = {"metric": "Gaussian-view evals/s", "value": round(value, 1), "unit": "evals/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
@@ -234,9 +240,88 @@ def main() -> int:
                        "step": "stats+score+select+compact", "score_path": args.score_path,
                        "ms_per_prune": round(ms_per_step, 4)},
             "phases_ms": {k: round(v, 4) for k, v in avg.items()},
-            "roofline": roofline, "cpu_baseline": cpu}
+            "roofline": roofline, "cpu_baseline": cpu, "serving": serving}
     print(json.dumps(line), flush=True)
     return 0
+
+
+def serve_bench(args) -> dict:
+    """Served latency: Poisson arrivals of prune jobs on resident scenes
+    (paper_2606_09074_amd.serve), once with FP32 scenes and once with the same
+    scenes in 2-byte storage, then a burst of the same jobs with and without
+    overlap.  Latency = completion seen by the host - arrival time."""
+    import numpy as np
+    import torch
+
+    from paper_2606_09074_amd import serve, synth
+    dev = torch.device("cuda:0")
+    specs = synth.serve_scene_specs(8)
+    log(f"serve: generating {len(specs)} resident scenes, n = {[sp.n for sp in specs]}")
+    f32, b16 = [], []
+    for sp in specs:
+        pl = synth.make_planes(sp)
+        f32.append(torch.from_numpy(pl).to(dev))
+        b16.append(torch.from_numpy(synth.quantize_bf16_f16(pl)).to(dev))
+    arrivals, reqs = synth.serve_requests(args.serve_jobs, len(specs), rate=args.serve_rate)
+    cams = {}
+    for _, V, _ in reqs:
+        if V not in cams:
+            cams[V] = torch.from_numpy(synth.ring_cameras(V)).to(dev)
+    torch.cuda.synchronize()
+
+    tuner = serve.Tuner()
+    buckets = sorted({(serve.bucket_of(sp.n, V)) for sp in specs for V in (64, 128, 256)})
+    tuner.tune(f32[-1], lambda V: torch.from_numpy(synth.ring_cameras(V)).to(dev), buckets, reps=3)
+    log(f"serve: tuned {len(buckets)} buckets: {sorted(tuner.table.items())}")
+
+    def run(scenes, arr, slots):
+        srv = serve.Server(dev, slots=slots, tuner=tuner)
+        for t in scenes:
+            srv.add_scene(t)
+        # warm the allocator and the kernels on every scene
+        for j in range(len(scenes)):
+            srv.submit(j, cams[reqs[0][1]], 0.5)
+        srv.drain()
+        keeps = {}
+
+        def done(job):
+            keeps[job.id] = job.keep[:job.n]
+            job.out = job.index_map = job.scores = None
+        jobs = [(sc, cams[V], r) for sc, V, r in reqs]
+        t0 = time.perf_counter()
+        fin = serve.run_open_loop(srv, jobs, arr, on_done=done)
+        span = time.perf_counter() - t0
+        torch.cuda.synchronize()
+        lat = [j.latency * 1e3 for j in fin]
+        dev_ms = [j.device_ms for j in fin]
+        first = min(j.id for j in fin)
+        order = [keeps[first + i] for i in range(len(fin))]
+        evals = sum(specs[sc].n * V for sc, V, _ in reqs)
+        return {"p50_ms": round(serve.percentile(lat, 0.5), 3), "p99_ms": round(serve.percentile(lat, 0.99), 3),
+                "mean_ms": round(float(np.mean(lat)), 3), "max_ms": round(float(np.max(lat)), 3),
+                "device_p50_ms": round(serve.percentile(dev_ms, 0.5), 3),
+                "device_p99_ms": round(serve.percentile(dev_ms, 0.99), 3),
+                "jobs_per_s": round(len(fin) / span, 2), "evals_per_s": round(evals / span, 1)}, order
+
+    log(f"serve: {len(reqs)} jobs at {args.serve_rate}/s, FP32 scenes")
+    r32, k32 = run(f32, arrivals, args.serve_slots)
+    log(f"serve: same jobs, BF16/FP16 scenes")
+    r16, k16 = run(b16, arrivals, args.serve_slots)
+    jac = []
+    for a, b in zip(k32, k16):
+        a, b = a.bool(), b.bool()
+        jac.append(float((a & b).sum().item()) / max(float((a | b).sum().item()), 1.0))
+    burst = np.zeros(len(reqs))
+    log("serve: burst (all jobs at once), with and without overlap")
+    b4, _ = run(f32, burst, args.serve_slots)
+    b1, _ = run(f32, burst, 1)
+    return {"workload": "resident scenes n=0.25M..4.9M (log-uniform strata), 50..300 ring views, ratio 0.3..0.9",
+            "jobs": len(reqs), "rate_per_s": args.serve_rate, "slots": args.serve_slots,
+            "latency_clock": "host: arrival to observed completion",
+            "f32": r32, "bf16_f16": r16,
+            "kept_jaccard_bf16_vs_f32": {"min": round(min(jac), 5), "mean": round(float(np.mean(jac)), 5)},
+            "burst": {"slots": args.serve_slots, "jobs_per_s": b4["jobs_per_s"], "evals_per_s": b4["evals_per_s"],
+                      "one_slot_jobs_per_s": b1["jobs_per_s"]}}
 
 
 if __name__ == "__main__":

@@ -106,6 +106,10 @@ typedef struct {
  *           input order) or REFINE_PATH_BINNED (2: primitives grouped by
  *           spatial cell, (group, view) pairs whose conservative footprint
  *           bound misses the view frustum skipped)
+ *  records_per_lane
+ *           binned path only, again never a change of results: 0 = the
+ *           library's choice, 1 or 2 primitives per lane (a wave's group is
+ *           64 or 128 spatially close primitives sharing one view list)
  */
 typedef struct {
     double eta;
@@ -119,7 +123,7 @@ typedef struct {
     int32_t equal_lambda;
     int32_t n_sub_views;
     int32_t score_path;
-    int32_t reserved;       /* must be 0 */
+    int32_t records_per_lane;
 } refine_params;
 
 typedef enum { REFINE_PATH_AUTO = 0, REFINE_PATH_DIRECT = 1, REFINE_PATH_BINNED = 2 } refine_score_path;
@@ -241,6 +245,11 @@ refine_status refine_select(const float* d_scores, int64_t n, double ratio, int6
  * survivors beyond it are not written.  d_n_out (nullable, device int64)
  * receives the number of survivors (which may exceed the capacity).
  * in and out must have the same dtype and sh_dtype and must not overlap.
+ * Speed, not results, depends on alignment: with in->planes 16-byte aligned,
+ * in->stride times the element size a multiple of 16 bytes and d_keep 4-byte
+ * aligned, each plane is read with 16-byte loads; for 2-byte storage an
+ * output 4-byte aligned with an even stride is written two elements per
+ * store.  Other layouts take a scalar path.
  */
 refine_status refine_compact(const refine_scene* in, const uint8_t* d_keep, const refine_scene* out,
                              int32_t* d_index_map, int64_t* d_n_out, void* d_ws, size_t ws_bytes,

@@ -49,7 +49,7 @@ refine_status check_params(const refine_params* p)
     if (p->equal_lambda != 0 && p->equal_lambda != 1) return REFINE_E_INVALID;
     if (p->n_sub_views < 0) return REFINE_E_INVALID;
     if (p->score_path < REFINE_PATH_AUTO || p->score_path > REFINE_PATH_BINNED) return REFINE_E_INVALID;
-    if (p->reserved != 0) return REFINE_E_INVALID;
+    if (p->records_per_lane < 0 || p->records_per_lane > 2) return REFINE_E_INVALID;
     return REFINE_OK;
 }
 

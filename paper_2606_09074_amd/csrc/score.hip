@@ -53,10 +53,7 @@ namespace {
 constexpr float kShC0 = 0.28209479177387814f;
 constexpr float kCullMargin = 1.01f;
 constexpr int64_t kBinnedMinPrims = 65536;
-#ifndef REFINE_BINNED_PPL
-#define REFINE_BINNED_PPL 1
-#endif
-constexpr int kBinnedPPL = REFINE_BINNED_PPL;   // binned records per lane
+constexpr int kDefaultPPL = 1;   // binned records per lane unless the caller picks
 
 // Also clears the binning cell counts (cell_cnt is null on the direct path).
 __global__ __launch_bounds__(kBlock) void camera_prep(const float* __restrict__ cams, int n_views, int nv,
@@ -550,13 +547,19 @@ void views_mode(const void* planes, int64_t stride, int n, const refine_params& 
     const int vis = prm.vis_mode == REFINE_VIS_ALPHA ? 1 : 0;
     const float eta = (float)prm.eta, zn = (float)prm.z_near;
     const dim3 grid((unsigned)((n + kBlock - 1) / kBlock));
-    if (binned)
-        hipLaunchKernelGGL((score_binned<PROJ, kBinnedPPL>), dim3((unsigned)((n + kBlock * kBinnedPPL - 1) /
-                                                                             (kBlock * kBinnedPPL))),
-                           dim3(kBlock), 0, stream, ws.recs, n, ws.cams, ws.culls, nv, eta, zn, d_scores, evaluated);
-    else
-        hipLaunchKernelGGL((score_direct<PROJ, ST>), grid, dim3(kBlock), 0, stream, planes, stride, n, ws.cams, nv, d_stats,
-                           eta, zn, vis, d_scores);
+    if (binned) {
+        const int ppl = prm.records_per_lane > 0 ? prm.records_per_lane : kDefaultPPL;
+        const unsigned blocks = (unsigned)((n + kBlock * ppl - 1) / (kBlock * ppl));
+        if (ppl == 2)
+            hipLaunchKernelGGL((score_binned<PROJ, 2>), dim3(blocks), dim3(kBlock), 0, stream, ws.recs, n, ws.cams,
+                               ws.culls, nv, eta, zn, d_scores, evaluated);
+        else
+            hipLaunchKernelGGL((score_binned<PROJ, 1>), dim3(blocks), dim3(kBlock), 0, stream, ws.recs, n, ws.cams,
+                               ws.culls, nv, eta, zn, d_scores, evaluated);
+    } else {
+        hipLaunchKernelGGL((score_direct<PROJ, ST>), grid, dim3(kBlock), 0, stream, planes, stride, n, ws.cams, nv,
+                           d_stats, eta, zn, vis, d_scores);
+    }
 }
 
 int views_of(const refine_params& prm, int32_t n_views)

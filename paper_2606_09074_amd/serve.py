@@ -1,0 +1,362 @@
+"""Serving prune jobs on one GPU: resident scenes, continuous batching.
+
+A job is one prune (paper Sec. 3.3: score every primitive, remove the
+bottom beta * N) of a scene that stays resident in device memory, seen
+from the job's own camera set.  The server
+
+* keeps scenes resident (``add_scene``), each plane padded to a multiple of
+  8 elements so the library's 16-byte-load kernels apply, and takes jobs as
+  they arrive (``submit``), in arrival order;
+* admits the head of the queue as soon as an in-flight slot and enough
+  device memory are free: a job reserves its workspace, scores, mask,
+  survivor planes and index map (``job_bytes``) against a budget, which by
+  default is the device's memory less the resident scenes and a reserve;
+* runs every admitted job's five library calls (stats, score prepare,
+  view loop, select, compact) on that slot's own HIP stream, so jobs that
+  arrive while others run overlap on the device -- a small scene does not
+  fill the 256 compute units, and its launches interleave with the others';
+* notices completions by polling an event recorded after each job's last
+  call, then frees the slot and the reservation and admits the next jobs.
+
+Each job's results do not depend on what runs beside it: the library's
+reductions have fixed orders (FP64 statistics summed per tile in a fixed
+order, per-primitive view sums in view order, integer selection), so a job
+gives bit-identical scores, mask and survivors alone and in the mix.
+
+``Tuner`` picks, per (primitive count, view count) bucket, the execution
+choice of the view loop -- direct, or binned with one or two primitives per
+lane -- by timing each on a synthetic scene of the bucket's size; choices
+never change results, only speed, and the table can be saved and reloaded.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import json
+import math
+import time
+from typing import Optional
+
+import numpy as np
+
+N_PLANES = 59
+STRIDE_ALIGN = 8      # elements: 16-byte aligned planes for 2- and 4-byte storage
+
+
+# ------------------------------------------------------------------ policy
+
+def job_bytes(n: int, n_views: int, n_keep: int, elem_bytes: int, workspace_bytes: int) -> int:
+    """Device bytes a job holds while in flight: workspace, FP32 scores, the
+    keep mask, the survivors' planes, the index map and the small outputs."""
+    return int(workspace_bytes + 4 * n + n + N_PLANES * elem_bytes * n_keep + 4 * n_keep + 18 * 4 * n_views
+               + 256 + 96 + 64)
+
+
+class Admission:
+    """First-come first-served admission against in-flight slots and a byte
+    budget.  The head of the queue blocks the ones behind it, so a large job
+    is never starved by a stream of small ones.  No device calls: the
+    policy is plain bookkeeping."""
+
+    def __init__(self, budget_bytes: int, slots: int):
+        if slots < 1 or budget_bytes <= 0:
+            raise ValueError("need at least one slot and a positive budget")
+        self.budget = int(budget_bytes)
+        self.slots = int(slots)
+        self.in_use = 0
+        self.inflight = 0
+
+    def fits_ever(self, nbytes: int) -> bool:
+        return nbytes <= self.budget
+
+    def can_admit(self, nbytes: int) -> bool:
+        return self.inflight < self.slots and self.in_use + nbytes <= self.budget
+
+    def admit(self, nbytes: int) -> None:
+        if not self.can_admit(nbytes):
+            raise RuntimeError("admission without room")
+        self.in_use += nbytes
+        self.inflight += 1
+
+    def release(self, nbytes: int) -> None:
+        if self.inflight < 1 or nbytes > self.in_use:
+            raise RuntimeError("release without a matching admission")
+        self.in_use -= nbytes
+        self.inflight -= 1
+
+
+def poisson_arrivals(rate_per_s: float, count: int, rng: np.random.Generator) -> np.ndarray:
+    """Arrival times (seconds from 0) of a Poisson process."""
+    return np.cumsum(rng.exponential(1.0 / rate_per_s, size=count))
+
+
+def percentile(values, q: float) -> float:
+    v = np.sort(np.asarray(values, dtype=np.float64))
+    if v.size == 0:
+        return float("nan")
+    return float(np.quantile(v, q))
+
+
+# ------------------------------------------------------------------- tuner
+
+def bucket_of(n: int, n_views: int) -> tuple[int, int]:
+    """(round(log2 n), round(log2 V)) of a job."""
+    return (int(round(math.log2(max(n, 1)))), int(round(math.log2(max(n_views, 1)))))
+
+
+# execution choices of the view loop: (score_path, records_per_lane)
+CANDIDATES = ((1, 0), (2, 1), (2, 2))
+
+
+class Tuner:
+    """Per-bucket choice of the view loop's execution (never its results)."""
+
+    def __init__(self, table: Optional[dict] = None):
+        self.table: dict[tuple[int, int], tuple[int, int]] = dict(table or {})
+
+    def choice(self, n: int, n_views: int) -> Optional[tuple[int, int]]:
+        return self.table.get(bucket_of(n, n_views))
+
+    def save(self, path: str) -> None:
+        with open(path, "w") as f:
+            json.dump({f"{a},{b}": list(v) for (a, b), v in sorted(self.table.items())}, f, indent=1)
+
+    @classmethod
+    def load(cls, path: str) -> "Tuner":
+        with open(path) as f:
+            raw = json.load(f)
+        return cls({tuple(int(x) for x in k.split(",")): tuple(v) for k, v in raw.items()})
+
+    def tune(self, planes, cams_for_views, buckets, reps: int = 3, stream=None, log=None) -> None:
+        """Time every candidate on prefixes of `planes` (a resident scene
+        tensor at least as large as the biggest bucket) with camera sets from
+        `cams_for_views(V)`, keep the fastest per bucket."""
+        import torch
+
+        from . import _lib, api
+        dev = planes.device
+        s = stream if stream is not None else torch.cuda.current_stream(dev)
+        for (lb_n, lb_v) in buckets:
+            n = min(1 << lb_n, planes.shape[1])
+            V = 1 << lb_v
+            cams = cams_for_views(V)
+            ws = api.workspace(n, V, dev)
+            st = torch.empty(_lib.STATS_BYTES, dtype=torch.uint8, device=dev)
+            scores = torch.empty(n, dtype=torch.float32, device=dev)
+            best = None
+            for path, ppl in CANDIDATES:
+                prm = _lib.default_params()
+                prm.score_path, prm.records_per_lane = path, ppl
+                times = []
+                for r in range(reps + 1):
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record(s)
+                    api.refine_stats(planes, st, ws, prm, n=n, stream=s)
+                    api.refine_score(planes, cams, st, scores, ws, prm, n=n, stream=s)
+                    e1.record(s)
+                    e1.synchronize()
+                    if r:
+                        times.append(e0.elapsed_time(e1))
+                t = float(np.median(times))
+                if best is None or t < best[0]:
+                    best = (t, (path, ppl))
+            self.table[(lb_n, lb_v)] = best[1]
+            if log:
+                log(f"tuner: bucket n=2^{lb_n} V=2^{lb_v} -> path {best[1][0]} ppl {best[1][1]} ({best[0]:.3f} ms)")
+
+
+# ------------------------------------------------------------------ server
+
+@dataclasses.dataclass
+class Job:
+    id: int
+    scene: int
+    cams: object                  # device tensor [V, 18]
+    ratio: float
+    params: object                # _lib.Params
+    t_arrival: float
+    n: int = 0
+    n_keep: int = 0
+    nbytes: int = 0
+    t_admit: float = 0.0
+    t_done: float = 0.0
+    slot: int = -1
+    start_event: object = None
+    done_event: object = None
+    stats: object = None
+    scores: object = None
+    keep: object = None
+    out: object = None
+    index_map: object = None
+    n_out: object = None
+    workspace: object = None
+
+    @property
+    def latency(self) -> float:
+        return self.t_done - self.t_arrival
+
+    @property
+    def device_ms(self) -> float:
+        """Stream time from the job's first call to its last (finished jobs)."""
+        return self.start_event.elapsed_time(self.done_event)
+
+
+class Server:
+    """Continuous-batching prune server on one device (see module doc)."""
+
+    def __init__(self, device="cuda:0", slots: int = 4, budget_bytes: Optional[int] = None,
+                 reserve_bytes: int = 8 << 30, tuner: Optional[Tuner] = None):
+        import torch
+
+        from . import _lib
+        _lib.load()
+        self.torch = torch
+        self.device = torch.device(device)
+        self.streams = [torch.cuda.Stream(self.device) for _ in range(slots)]   # default priority
+        self.free_slots = collections.deque(range(slots))
+        self.scenes: dict[int, object] = {}      # id -> padded [59, stride] tensor
+        self.scene_n: dict[int, int] = {}
+        self.scene_bytes = 0
+        self.reserve = int(reserve_bytes)
+        self.explicit_budget = budget_bytes
+        self.admission = Admission(self._budget(), slots)
+        self.queue: collections.deque[Job] = collections.deque()
+        self.running: list[Job] = []
+        self.tuner = tuner
+        self._next_id = 0
+
+    def _budget(self) -> int:
+        if self.explicit_budget is not None:
+            return int(self.explicit_budget)
+        total = self.torch.cuda.get_device_properties(self.device).total_memory
+        return max(int(total - self.scene_bytes - self.reserve), 1)
+
+    # scenes ---------------------------------------------------------------
+    def add_scene(self, planes, n: Optional[int] = None) -> int:
+        """Keep the first n primitives of a [59, stride] scene tensor (float32,
+        or int16 2-byte storage) resident; returns its id.  A stride that is
+        not a multiple of STRIDE_ALIGN is padded (one device copy)."""
+        from . import api
+        api.storage_dtypes(planes)
+        if planes.device != self.device:
+            raise ValueError("scenes must live on the server's device")
+        n = planes.shape[1] if n is None else int(n)
+        if planes.stride(1) != 1 or planes.stride(0) % STRIDE_ALIGN or planes.data_ptr() % 16:
+            stride = -(-max(n, 1) // STRIDE_ALIGN) * STRIDE_ALIGN
+            padded = self.torch.zeros((N_PLANES, stride), dtype=planes.dtype, device=self.device)
+            padded[:, :n] = planes[:, :n]
+            planes = padded
+        sid = len(self.scenes)
+        self.scenes[sid] = planes
+        self.scene_n[sid] = n
+        self.scene_bytes += planes.numel() * planes.element_size()
+        if self.explicit_budget is None:
+            self.admission.budget = self._budget()
+        return sid
+
+    # jobs -----------------------------------------------------------------
+    def submit(self, scene: int, cams, ratio: float, params=None, t_arrival: Optional[float] = None) -> Job:
+        from . import _lib, api
+        if scene not in self.scenes:
+            raise KeyError(f"no resident scene {scene}")
+        planes = self.scenes[scene]
+        n = self.scene_n[scene]
+        V = cams.shape[0]
+        prm = params if params is not None else _lib.default_params()
+        if self.tuner is not None and params is None:
+            c = self.tuner.choice(n, V)
+            if c is not None:
+                prm.score_path, prm.records_per_lane = c
+        n_keep = n - api.prune_count(n, ratio)
+        job = Job(self._next_id, scene, cams, float(ratio), prm,
+                  time.perf_counter() if t_arrival is None else t_arrival, n=n, n_keep=n_keep)
+        job.nbytes = job_bytes(n, V, n_keep, planes.element_size(), api.workspace_size(n, V))
+        if not self.admission.fits_ever(job.nbytes):
+            raise ValueError(f"job needs {job.nbytes} bytes, more than the budget {self.admission.budget}")
+        self._next_id += 1
+        self.queue.append(job)
+        return job
+
+    def _launch(self, job: Job) -> None:
+        from . import _lib, api
+        torch = self.torch
+        slot = self.free_slots.popleft()
+        s = self.streams[slot]
+        planes = self.scenes[job.scene]
+        n, V = job.n, job.cams.shape[0]
+        dev = self.device
+        with torch.cuda.stream(s):
+            job.workspace = api.workspace(n, V, dev)
+            job.stats = torch.empty(_lib.STATS_BYTES, dtype=torch.uint8, device=dev)
+            job.scores = torch.empty(max(n, 1), dtype=torch.float32, device=dev)
+            job.keep = torch.empty(max(n, 1), dtype=torch.uint8, device=dev)
+            out_stride = -(-max(job.n_keep, 1) // STRIDE_ALIGN) * STRIDE_ALIGN
+            job.out = torch.empty((N_PLANES, out_stride), dtype=planes.dtype, device=dev)
+            job.index_map = torch.empty(max(job.n_keep, 1), dtype=torch.int32, device=dev)
+            job.n_out = torch.empty(1, dtype=torch.int64, device=dev)
+        # the camera table may have been written on another stream
+        s.wait_stream(torch.cuda.current_stream(dev))
+        job.start_event = torch.cuda.Event(enable_timing=True)
+        job.start_event.record(s)
+        api.refine_stats(planes, job.stats, job.workspace, job.params, n=n, stream=s)
+        api.refine_score(planes, job.cams, job.stats, job.scores, job.workspace, job.params, n=n, stream=s)
+        api.refine_select(job.scores, job.keep, job.workspace, ratio=job.ratio, n=n, stream=s)
+        api.refine_compact(planes, job.keep, job.out, job.workspace, index_map_out=job.index_map,
+                           n_out=job.n_out, n=n, capacity=job.n_keep, stream=s)
+        job.done_event = torch.cuda.Event(enable_timing=True)
+        job.done_event.record(s)
+        job.slot = slot
+        job.t_admit = time.perf_counter()
+        self.running.append(job)
+
+    def step(self) -> list[Job]:
+        """Retire finished jobs, then admit queued ones while they fit.
+        Returns the jobs that finished in this step."""
+        done = []
+        still = []
+        for job in self.running:
+            if job.done_event.query():
+                job.t_done = time.perf_counter()
+                self.admission.release(job.nbytes)
+                self.free_slots.append(job.slot)
+                # the workspace goes back to the allocator, on the job's stream
+                job.workspace = None
+                done.append(job)
+            else:
+                still.append(job)
+        self.running = still
+        while self.queue and self.admission.can_admit(self.queue[0].nbytes):
+            job = self.queue.popleft()
+            self.admission.admit(job.nbytes)
+            self._launch(job)
+        return done
+
+    def idle(self) -> bool:
+        return not self.queue and not self.running
+
+    def drain(self) -> list[Job]:
+        out = []
+        while not self.idle():
+            out.extend(self.step())
+        return out
+
+
+def run_open_loop(server: Server, requests, arrivals, on_done=None) -> list[Job]:
+    """Submit `requests` [(scene, cams, ratio)] at host times `arrivals`
+    (seconds from the start), stepping the server in between; returns the
+    finished jobs in completion order."""
+    t0 = time.perf_counter()
+    finished = []
+    i = 0
+    total = len(requests)
+    while len(finished) < total:
+        now = time.perf_counter() - t0
+        while i < total and arrivals[i] <= now:
+            scene, cams, ratio = requests[i]
+            server.submit(scene, cams, ratio, t_arrival=t0 + arrivals[i])
+            i += 1
+        for job in server.step():
+            finished.append(job)
+            if on_done:
+                on_done(job)
+    return finished

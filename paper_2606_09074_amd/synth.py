@@ -239,3 +239,42 @@ def dequantize_bf16_f16(bits: np.ndarray) -> np.ndarray:
     out[:N_GEOM_PLANES] = bf16_bits_to_f32(u[:N_GEOM_PLANES])
     out[N_GEOM_PLANES:] = u[N_GEOM_PLANES:].view(np.float16).astype(np.float32)
     return out
+
+
+# ------------------------------------------------------------------ serving
+#
+# The serving workload: prune jobs on resident scenes drawn like the small
+# scene (clusters in [-3,3]^3 with sigma 0.5, background in [-5,5]^3, ring
+# cameras at radius 8, 320x240, f = 300) with a primitive count log-uniform
+# in [0.2M, 6M]; each job brings 50..300 ring cameras and a prune ratio
+# uniform in [0.3, 0.9]; jobs arrive as a Poisson process (20 per second).
+
+SERVE_N_RANGE = (200_000, 6_000_000)
+SERVE_VIEWS_RANGE = (50, 300)
+SERVE_RATIO_RANGE = (0.3, 0.9)
+SERVE_RATE = 20.0
+
+
+def serve_scene_specs(count: int, seed: int = 3000, n_range=SERVE_N_RANGE) -> list:
+    """Specs of `count` resident scenes whose primitive counts stratify the
+    log-uniform law on n_range (the midpoints of `count` equal-probability
+    strata), so jobs that pick a scene uniformly see that law."""
+    lo, hi = np.log(n_range[0]), np.log(n_range[1])
+    ns = np.exp(lo + (np.arange(count) + 0.5) / count * (hi - lo)).astype(np.int64)
+    return [dataclasses.replace(SMALL, name=f"serve-{j}-{int(n)}", n=int(n), seed=seed + 1 + j)
+            for j, n in enumerate(ns)]
+
+
+def serve_requests(count: int, n_scenes: int, seed: int = 3100, rate: float = SERVE_RATE,
+                   views_range=SERVE_VIEWS_RANGE, ratio_range=SERVE_RATIO_RANGE):
+    """(arrival seconds, [(scene index, views, ratio)]) of `count` jobs."""
+    rng = np.random.default_rng(seed)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=count))
+    jobs = [(int(rng.integers(0, n_scenes)), int(rng.integers(views_range[0], views_range[1] + 1)),
+             float(rng.uniform(*ratio_range))) for _ in range(count)]
+    return arrivals, jobs
+
+
+def ring_cameras(n_views: int) -> np.ndarray:
+    """The small scene's ring rig with n_views cameras."""
+    return make_cameras(SMALL.with_n(SMALL.n, n_views=n_views))

@@ -258,7 +258,8 @@ def _paths(planes, cams, n=None, **kw):
 @pytest.mark.parametrize("name,n,mode", [("small", None, {}), ("small", 9000, {}), ("small", 777, {}),
                                          ("small", None, dict(proj_mode=1)), ("small", None, dict(proj_mode=2)),
                                          ("small", None, dict(vis_mode=1, n_sub_views=6)),
-                                         ("medium", 400_000, {})])
+                                         ("medium", 400_000, {}), ("small", 9000, dict(records_per_lane=2)),
+                                         ("medium", 400_000, dict(records_per_lane=2))])
 def test_binned_and_direct_paths_bit_identical(name, n, mode):
     """Culling skips only (group, view) pairs whose every primitive is gated
     out, so the binned path must reproduce the direct path bit for bit."""

@@ -1,0 +1,121 @@
+"""The serving loop on the GPU: each job's results are the same alone and in
+the mix (overlapping on several streams), admission respects the memory
+budget, and the tuner's choices leave results unchanged."""
+import numpy as np
+import pytest
+
+from paper_2606_09074_amd import synth
+from tests.gpu_common import log
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pool():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    dev = torch.device("cuda:0")
+    specs = synth.serve_scene_specs(4, seed=77, n_range=(20_000, 400_000))
+    scenes = []
+    for j, sp in enumerate(specs):
+        pl = synth.make_planes(sp)
+        if j == 2:                                    # one resident scene in 2-byte storage
+            pl = synth.quantize_bf16_f16(pl)
+        scenes.append(torch.from_numpy(pl).to(dev))
+    arr, jobs = synth.serve_requests(14, n_scenes=len(scenes), seed=78, views_range=(16, 120))
+    cams = {}
+    for _, V, _ in jobs:
+        if V not in cams:
+            cams[V] = torch.from_numpy(synth.ring_cameras(V)).to(dev)
+    torch.cuda.synchronize()
+    log(f"serve pool: n={[s.shape[1] for s in scenes]} jobs={jobs}")
+    return scenes, jobs, cams
+
+
+def _results(job):
+    import torch
+    torch.cuda.synchronize()
+    k = job.n_keep
+    return (job.scores[:job.n].cpu().numpy().view(np.uint32), job.keep[:job.n].cpu().numpy(),
+            job.out[:, :k].cpu().numpy(), job.index_map[:k].cpu().numpy(), int(job.n_out.item()))
+
+
+def _server(scenes, **kw):
+    from paper_2606_09074_amd import serve
+    srv = serve.Server("cuda:0", **kw)
+    for s in scenes:
+        srv.add_scene(s)
+    return srv
+
+
+def test_results_same_alone_and_in_the_mix(pool):
+    scenes, jobs, cams = pool
+    # alone: one slot, one job at a time
+    alone = []
+    srv1 = _server(scenes, slots=1)
+    for sc, V, r in jobs:
+        srv1.submit(sc, cams[V], r)
+        (job,) = srv1.drain()
+        alone.append(_results(job))
+    # in the mix: everything submitted at once, four jobs in flight
+    srv4 = _server(scenes, slots=4)
+    subm = [srv4.submit(sc, cams[V], r) for sc, V, r in jobs]
+    peak = 0
+    finished = []
+    while not srv4.idle():
+        finished.extend(srv4.step())
+        peak = max(peak, len(srv4.running))
+    assert peak > 1, "jobs never overlapped"
+    assert sorted(j.id for j in finished) == [j.id for j in subm]
+    for j, a in zip(subm, alone):
+        b = _results(j)
+        for x, y in zip(a[:4], b[:4]):
+            np.testing.assert_array_equal(x, y)
+        assert a[4] == b[4] == j.n_keep
+    log(f"[serve] {len(jobs)} jobs identical alone and mixed; peak in flight {peak}")
+
+
+def test_admission_budget_bounds_memory(pool):
+    from paper_2606_09074_amd import api, serve
+    scenes, jobs, cams = pool
+    sizes = []
+    for sc, V, r in jobs:
+        n = scenes[sc].shape[1]
+        k = n - api.prune_count(n, r)
+        sizes.append(serve.job_bytes(n, V, k, scenes[sc].element_size(), api.workspace_size(n, V)))
+    budget = int(max(sizes) * 1.5)
+    srv = _server(scenes, slots=4, budget_bytes=budget)
+    for sc, V, r in jobs:
+        srv.submit(sc, cams[V], r)
+    done = []
+    while not srv.idle():
+        done.extend(srv.step())
+        assert srv.admission.in_use <= budget
+        assert sum(j.nbytes for j in srv.running) == srv.admission.in_use
+    assert len(done) == len(jobs)
+    with pytest.raises(ValueError):
+        small = _server(scenes, slots=1, budget_bytes=1000)
+        small.submit(0, cams[jobs[0][1]], 0.5)
+
+
+def test_tuner_choices_do_not_change_results(pool):
+    import torch
+
+    from paper_2606_09074_amd import serve
+    scenes, jobs, cams = pool
+    big = max(scenes, key=lambda s: s.shape[1] if s.dtype == torch.float32 else 0)
+    tuner = serve.Tuner()
+    tuner.tune(big, lambda V: torch.from_numpy(synth.ring_cameras(V)).to(big.device),
+               buckets=[(15, 5), (18, 6)], reps=2, log=log)
+    assert set(tuner.table) == {(15, 5), (18, 6)}
+    assert all(c in serve.CANDIDATES for c in tuner.table.values())
+    tuned = _server(scenes, slots=2, tuner=tuner)
+    plain = _server(scenes, slots=2)
+    for sc, V, r in jobs[:6]:
+        a = tuned.submit(sc, cams[V], r)
+        b = plain.submit(sc, cams[V], r)
+        tuned.drain()
+        plain.drain()
+        ra, rb = _results(a), _results(b)
+        for x, y in zip(ra[:4], rb[:4]):
+            np.testing.assert_array_equal(x, y)
