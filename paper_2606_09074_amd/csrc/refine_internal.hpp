@@ -35,13 +35,15 @@ constexpr int kStatSlots = 8;      // doubles per stats partial
 // quantities are scaled by sv = 1 / sqrt(fx^2 + fy^2): the gate is invariant
 // under that scaling and the projection term of mode COV becomes
 // (a + c) / (z^2 + eta) with no per-camera factor.
+// The image coordinates are taken about the image centre: with
+// ox = sv (cx - W/2), X = sv fx x + ox z gives X / z = sv (u - W/2).
 struct CamRec {
-    float px[4];       // sv fx R_v row 0, sv fx t_x   -> X = sv fx x
-    float py[4];       // sv fy R_v row 1, sv fy t_y   -> Y = sv fy y
+    float px[4];       // sv fx R_v row 0 + ox R_v row 2, sv fx t_x + ox t_z
+    float py[4];       // sv fy R_v row 1 + oy R_v row 2, sv fy t_y + oy t_z
     float pz[4];       // R_v row 2, t_z               -> z
-    float ox, oy;      // sv (cx - W/2), sv (cy - H/2)
+    float cx0, cx1;    // EWA clamp interval of X / z: ox -+ sv clamp_k W/2
+    float cy0, cy1;    // of Y / z: oy -+ sv clamp_k H/2
     float hw, hh;      // sv W/2, sv H/2
-    float lx, ly;      // sv clamp_k W/2, sv clamp_k H/2
     float pad[14];
 };
 static_assert(sizeof(CamRec) == kCamRec * sizeof(float), "camera record size");

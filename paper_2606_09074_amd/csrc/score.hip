@@ -7,18 +7,20 @@
 // frustum half-spaces of the conservative culling test.
 //
 // Per (primitive, view) pair, FP32 (eval_pair; identical in both paths):
-//   X = sv fx x, Y = sv fy y, z       camera-space centre (Eq. 13 numerators)
+//   X = sv (fx x + (cx - W/2) z), Y likewise, z   camera-space centre with the
+//                                     image centre as origin (Eq. 13 numerators)
 //   q = 1/(z (z^2 + eta)):  1/z = q (z^2 + eta),  1/(z^2 + eta) = q z
-//   ux = X/z, uy = Y/z                projected centre about the principal point
-//   x^ = clamp(ux, +-lx), y^ = clamp(uy, +-ly)   EWA clamp (scaled pixels)
-//   r0 = sv fx R_v,0 - x^ R_v,2,  r1 = sv fy R_v,1 - y^ R_v,2
+//   ux = X/z, uy = Y/z                projected centre about the image centre
+//   x^ = clamp(ux, ox -+ lx), y^ likewise   EWA clamp of x/z (scaled pixels,
+//                                     shifted by ox = sv (cx - W/2))
+//   r0 = sv fx R_v,0 + ox R_v,2 - x^ R_v,2,  r1 likewise
 //       [r0; r1] / z is the scaled EWA Jacobian times the view rotation (Eq. 14)
 //   A0 = r0 L, A1 = r1 L with L = R(q) diag(s);  a = |A0|^2, b = A0.A1, c = |A1|^2
 //       z^2 Sigma' = [[a, b], [b, c]] as sums of squares (no cancellation for
 //       needle-like primitives, unlike T Sigma T^T in FP32)
 //   gate: z > z_near, and the centre lies within the 3-sigma radius
 //       r = 3 sqrt(lambda_max(Sigma')) of the image rectangle; with
-//       d = max(|ux + ox| - hw, |uy + oy| - hh) the test d < r reads
+//       d = max(|ux| - hw, |uy| - hh) the test d < r reads
 //       d z < 0  or  (d z)^2 < 4.5 (a + c + sqrt((a - c)^2 + 4 b^2))
 //   projection term: COV (a + c)/(z^2 + eta) (1/sbar^2 applied in the
 //       epilogue), DEPTH 1/(z^2 + eta) (Eq. 17), NONE 1
@@ -69,21 +71,23 @@ __global__ __launch_bounds__(kBlock) void camera_prep(const float* __restrict__ 
     const float sv = rsqrtf(fx * fx + fy * fy);
     const float sx = sv * fx, sy = sv * fy;
     CamRec r;
+    const float ox = sv * (cx - 0.5f * W), oy = sv * (cy - 0.5f * H);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        r.px[k] = sx * c[k];
-        r.py[k] = sy * c[3 + k];
+        r.px[k] = fmaf(ox, c[6 + k], sx * c[k]);
+        r.py[k] = fmaf(oy, c[6 + k], sy * c[3 + k]);
         r.pz[k] = c[6 + k];
     }
-    r.px[3] = sx * c[9];
-    r.py[3] = sy * c[10];
+    r.px[3] = fmaf(ox, c[11], sx * c[9]);
+    r.py[3] = fmaf(oy, c[11], sy * c[10]);
     r.pz[3] = c[11];
     r.hw = sv * (0.5f * W);
     r.hh = sv * (0.5f * H);
-    r.ox = sv * (cx - 0.5f * W);
-    r.oy = sv * (cy - 0.5f * H);
-    r.lx = clamp_k * r.hw;
-    r.ly = clamp_k * r.hh;
+    const float lx = clamp_k * r.hw, ly = clamp_k * r.hh;
+    r.cx0 = ox - lx;
+    r.cx1 = ox + lx;
+    r.cy0 = oy - ly;
+    r.cy1 = oy + ly;
 #pragma unroll
     for (int k = 0; k < 14; ++k) r.pad[k] = 0.0f;
     out[j] = r;
@@ -129,10 +133,10 @@ struct Prim {
 // vector registers.
 struct CamEval {
     float px[4], py[4], pz[4];
-    float ox, oy, hw, hh, lx, ly;
+    float cx0, cx1, cy0, cy1, hw, hh;
 };
 constexpr int kStageVec = 5;   // float4s staged per view
-static_assert(offsetof(CamRec, ly) + sizeof(float) <= kStageVec * sizeof(float4), "staged camera fields");
+static_assert(offsetof(CamRec, hh) + sizeof(float) <= kStageVec * sizeof(float4), "staged camera fields");
 
 // Activation (Sec. 3.1 readings) of primitive i; pre is the epilogue factor.
 template <int ST>
@@ -187,8 +191,8 @@ __device__ __forceinline__ void eval_pair(const Cam& c, Prim& p, float eta, floa
     const float rz = q * zz;
     const float ux = X * rz;
     const float uy = Y * rz;
-    const float xh = __builtin_amdgcn_fmed3f(ux, -c.lx, c.lx);
-    const float yh = __builtin_amdgcn_fmed3f(uy, -c.ly, c.ly);
+    const float xh = __builtin_amdgcn_fmed3f(ux, c.cx0, c.cx1);
+    const float yh = __builtin_amdgcn_fmed3f(uy, c.cy0, c.cy1);
     const float r00 = fmaf(-xh, c.pz[0], c.px[0]);
     const float r01 = fmaf(-xh, c.pz[1], c.px[1]);
     const float r02 = fmaf(-xh, c.pz[2], c.px[2]);
@@ -212,7 +216,7 @@ __device__ __forceinline__ void eval_pair(const Cam& c, Prim& p, float eta, floa
         P = q * z;
     else
         P = 1.0f;
-    const float d = fmaxf(fabsf(ux + c.ox) - c.hw, fabsf(uy + c.oy) - c.hh);
+    const float d = fmaxf(fabsf(ux) - c.hw, fabsf(uy) - c.hh);
     const float dz = d * z;
     const float e1 = sa - sc;
     const float w = ss + __builtin_amdgcn_sqrtf(fmaf(e1, e1, 4.0f * sb * sb));
@@ -492,8 +496,8 @@ __global__ __launch_bounds__(kBlock) void score_binned(const PrimRec* __restrict
             c.px[0] = r0.x; c.px[1] = r0.y; c.px[2] = r0.z; c.px[3] = r0.w;
             c.py[0] = r1.x; c.py[1] = r1.y; c.py[2] = r1.z; c.py[3] = r1.w;
             c.pz[0] = r2.x; c.pz[1] = r2.y; c.pz[2] = r2.z; c.pz[3] = r2.w;
-            c.ox = r3.x; c.oy = r3.y; c.hw = r3.z; c.hh = r3.w;
-            c.lx = r4.x; c.ly = r4.y;
+            c.cx0 = r3.x; c.cx1 = r3.y; c.cy0 = r3.z; c.cy1 = r3.w;
+            c.hw = r4.x; c.hh = r4.y;
 #pragma unroll
             for (int k = 0; k < PPL; ++k) eval_pair<PROJ>(c, p[k], eta, z_near);
         }
