@@ -72,7 +72,7 @@ size_t workspace_layout(int64_t n, int32_t n_views, bool score, void* base, Work
     const size_t nv = (size_t)(n_views > 0 ? n_views : 0);
     size_t off = 0;
     const size_t o_sel = off;   off += align_up(sizeof(SelectState));
-    const size_t o_hist = off;  off += align_up(sizeof(uint32_t) * kHistBins);
+    const size_t o_hist = off;  off += align_up(sizeof(uint32_t) * kSelectHistWords);
     const size_t o_part = off;  off += align_up(sizeof(double) * kStatSlots * nt);
     const size_t o_cnt = off;   off += align_up(sizeof(uint32_t) * nt);
     const size_t o_toff = off;  off += align_up(sizeof(uint32_t) * nt);

@@ -29,6 +29,8 @@ constexpr int kTile = kBlock * kItems;
 constexpr int kCamRec = 32;        // floats per prepared camera record
 constexpr int kHistBits = 11;
 constexpr int kHistBins = 1 << kHistBits;
+constexpr int kHistCopies = 8;    // selection histogram copies: spreads the atomics on crowded bins
+constexpr int kSelectHistWords = 3 * kHistCopies * kHistBins;   // one set of copies per radix pass
 constexpr int kStatSlots = 8;      // doubles per stats partial
 
 // Prepared camera record (fp32, 128 bytes), built by camera_prep.  Pixel
@@ -91,7 +93,7 @@ constexpr int kCells = 1 << (3 * kCellBits);       // 4096 Morton cells (16 KB o
 
 struct Workspace {
     SelectState* sel;
-    uint32_t* hist;          // [kHistBins]
+    uint32_t* hist;          // [3 passes][kHistCopies][kHistBins]
     double* stat_part;       // [ntiles][kStatSlots]
     uint32_t* tile_cnt;      // [ntiles]
     uint32_t* tile_off;      // [ntiles]

@@ -3,12 +3,15 @@
 // Scores become order-preserving 32-bit keys.  The key of the n_prune-th
 // smallest primitive (the threshold T) is found by three most-significant-
 // digit-first radix passes (11, 11, 10 bits).  Each pass histograms, into
-// per-wave LDS histograms, the keys that share the prefix resolved so far,
-// merges them into one global histogram with integer atomics (exact and
-// order-independent), and a one-block pass scans that histogram and picks
-// the bucket holding the target rank.  (Folding that pass into the last
-// histogram block would need a device-scope fence per block, which on this
-// multi-die part writes back the L2: a separate launch is cheaper.)  Ties at T are broken by
+// one LDS histogram per tile, the keys that share the prefix resolved so far,
+// adds them into a global histogram with integer atomics (exact and
+// order-independent; 8 copies, one per block residue, so the crowded bins of
+// the first pass take 8x fewer atomics per address), and a one-block pass
+// sums the copies, scans them and picks the bucket holding the target rank.
+// (Folding that pass into the last histogram block would need a device-scope
+// fence per block, which on this multi-die part writes back the L2: a
+// separate launch is cheaper; so is this than having every histogram block
+// rescan the previous histograms itself.)  Ties at T are broken by
 // index: the pruned primitives are every key < T plus the k_eq lowest-index
 // keys == T, located with wave ballots and the exact count of equal keys in
 // the tiles before.  Integer arithmetic throughout, so the mask equals a
@@ -23,12 +26,13 @@ namespace {
 
 constexpr int kPassShift[3] = {21, 10, 0};
 constexpr int kPassBits[3] = {11, 11, 10};
-constexpr int kHistBlocksMax = 512;   // grid of the histogram passes (each block loops over tiles)
 
+// Clears the histograms of all three passes and sets up the state.
 __global__ void select_init(SelectState* __restrict__ st, uint32_t* __restrict__ hist, int64_t n, int64_t n_prune)
 {
-    for (int b = threadIdx.x; b < kHistBins; b += blockDim.x) hist[b] = 0u;
-    if (threadIdx.x == 0) {
+    for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < kSelectHistWords; b += gridDim.x * blockDim.x)
+        hist[b] = 0u;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
         SelectState s = {};
         s.n = n;
         s.n_prune = n_prune;
@@ -42,13 +46,14 @@ __global__ void select_init(SelectState* __restrict__ st, uint32_t* __restrict__
     }
 }
 
-// Locate the bucket holding the target rank, fold it into the prefix, clear
-// the histogram for the next pass (one block).
-__global__ __launch_bounds__(kBlock) void select_find(SelectState* __restrict__ st, uint32_t* __restrict__ hist,
-                                                        int shift, int bits, int last_pass)
+// Locate the bucket holding the target rank in this pass's histogram (the
+// sum of its copies) and fold it into the prefix (one block).
+__global__ __launch_bounds__(kScanThreads) void select_find(SelectState* __restrict__ st,
+                                                              const uint32_t* __restrict__ hist, int shift, int bits,
+                                                              int last_pass)
 {
-    constexpr int kPer = kHistBins / kBlock;   // 8 bins per thread
-    __shared__ uint32_t wave_tot[kWaves];
+    constexpr int kPer = kHistBins / kScanThreads;   // 2 bins per thread
+    __shared__ uint32_t wave_tot[kScanThreads / 64];
     __shared__ int64_t found_run;
     __shared__ int found_bin;
     const int64_t rank = st->rank;
@@ -58,7 +63,11 @@ __global__ __launch_bounds__(kBlock) void select_find(SelectState* __restrict__ 
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
         const int b = threadIdx.x * kPer + j;
-        h[j] = b < nb ? hist[b] : 0u;
+        uint32_t c = 0;
+        if (b < nb)
+#pragma unroll
+            for (int r = 0; r < kHistCopies; ++r) c += hist[r * kHistBins + b];
+        h[j] = c;
         local += h[j];
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -83,8 +92,6 @@ __global__ __launch_bounds__(kBlock) void select_find(SelectState* __restrict__ 
         }
         run += h[j];
     }
-#pragma unroll
-    for (int j = 0; j < kPer; ++j) hist[threadIdx.x * kPer + j] = 0u;
     __syncthreads();
     if (threadIdx.x == 0 && found_bin >= 0) {
         SelectState s = *st;
@@ -99,33 +106,49 @@ __global__ __launch_bounds__(kBlock) void select_find(SelectState* __restrict__ 
     }
 }
 
-__global__ __launch_bounds__(kBlock) void select_hist(const float* __restrict__ scores, int n, int ntiles,
+// One tile per block: all 16 keys of a thread are loaded before any is
+// counted, and the crowded bins (many equal exponents, exact zeros) are
+// counted per wave -- the lanes that share the lowest counting lane's bin
+// add with one LDS atomic.
+__global__ __launch_bounds__(kBlock) void select_hist(const float* __restrict__ scores, int n,
                                                         const SelectState* __restrict__ st, int shift, int bits,
                                                         uint32_t* __restrict__ hist)
 {
-    __shared__ uint32_t h[kWaves][kHistBins];
-    const int wave = threadIdx.x >> 6;
-    for (int b = threadIdx.x; b < kWaves * kHistBins; b += kBlock) (&h[0][0])[b] = 0u;
-    __syncthreads();
+    constexpr uint32_t kNoBin = 0xFFFFFFFFu;
+    __shared__ uint32_t h[kHistBins];
+    const int nb = 1 << bits;
+    for (int b = threadIdx.x; b < nb; b += kBlock) h[b] = 0u;
     const uint32_t prefix = st->prefix, mask = st->mask;
-    const uint32_t dmask = (1u << bits) - 1u;
-    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const int base = tile * kTile;
-#pragma unroll 4
-        for (int k = 0; k < kItems; ++k) {
-            const int i = base + k * kBlock + (int)threadIdx.x;
-            if (i < n) {
-                const uint32_t key = float_key(scores[i]);
-                if ((key & mask) == prefix) atomicAdd(&h[wave][(key >> shift) & dmask], 1u);
-            }
+    const uint32_t dmask = (uint32_t)nb - 1u;
+    const int base = blockIdx.x * kTile;
+    float v[kItems];
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        const int i = base + k * kBlock + (int)threadIdx.x;
+        v[k] = i < n ? scores[i] : 0.0f;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        const int i = base + k * kBlock + (int)threadIdx.x;
+        const uint32_t key = float_key(v[k]);
+        const uint32_t bin = (i < n && (key & mask) == prefix) ? (key >> shift) & dmask : kNoBin;
+        const uint64_t valid = __ballot(bin != kNoBin);
+        if (valid == 0ull) continue;
+        const int leader = __builtin_ctzll(valid);
+        const uint32_t lead_bin = __builtin_amdgcn_readlane(bin, leader);
+        const uint64_t same = __ballot(bin == lead_bin);
+        if (bin == lead_bin) {
+            if (lane == leader) atomicAdd(&h[lead_bin], (uint32_t)__popcll(same));
+        } else if (bin != kNoBin) {
+            atomicAdd(&h[bin], 1u);
         }
     }
     __syncthreads();
-    for (int b = threadIdx.x; b <= (int)dmask; b += kBlock) {
-        uint32_t c = 0;
-#pragma unroll
-        for (int w = 0; w < kWaves; ++w) c += h[w][b];
-        if (c) atomicAdd(&hist[b], c);
+    for (int b = threadIdx.x; b < nb; b += kBlock) {
+        const uint32_t c = h[b];
+        if (c) atomicAdd(&hist[(blockIdx.x % kHistCopies) * kHistBins + b], c);
     }
 }
 
@@ -218,17 +241,18 @@ hipError_t launch_select(const float* d_scores, int64_t n, int64_t n_prune, uint
                          uint32_t* d_threshold, const Workspace& ws, hipStream_t stream)
 {
     const int ntiles = (int)num_tiles(n);
-    hipLaunchKernelGGL(select_init, dim3(1), dim3(kBlock), 0, stream, ws.sel, ws.hist, n, n_prune);
+    hipLaunchKernelGGL(select_init, dim3(kSelectHistWords / kBlock), dim3(kBlock), 0, stream, ws.sel, ws.hist, n,
+                       n_prune);
     if (ntiles == 0) {
         hipLaunchKernelGGL(select_outputs, dim3(1), dim3(1), 0, stream, ws.sel, d_n_keep, d_threshold);
         return hipGetLastError();
     }
     if (n_prune > 0) {
-        const int hb = ntiles < kHistBlocksMax ? ntiles : kHistBlocksMax;
         for (int p = 0; p < 3; ++p) {
-            hipLaunchKernelGGL(select_hist, dim3(hb), dim3(kBlock), 0, stream, d_scores, (int)n, ntiles, ws.sel,
-                               kPassShift[p], kPassBits[p], ws.hist);
-            hipLaunchKernelGGL(select_find, dim3(1), dim3(kBlock), 0, stream, ws.sel, ws.hist, kPassShift[p],
+            uint32_t* h = ws.hist + p * kHistCopies * kHistBins;
+            hipLaunchKernelGGL(select_hist, dim3(ntiles), dim3(kBlock), 0, stream, d_scores, (int)n, ws.sel,
+                               kPassShift[p], kPassBits[p], h);
+            hipLaunchKernelGGL(select_find, dim3(1), dim3(kScanThreads), 0, stream, ws.sel, h, kPassShift[p],
                                kPassBits[p], p == 2 ? 1 : 0);
         }
     }

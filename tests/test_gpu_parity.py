@@ -140,6 +140,31 @@ def test_deterministic_and_permutation_consistent():
     np.testing.assert_array_equal(rp["scores"].view(np.uint32), r["scores"][perm].view(np.uint32))
 
 
+@pytest.mark.slow
+@pytest.mark.parametrize("n", [16_777_216 + 4096 * 3 + 17])
+def test_select_many_tiles(n):
+    """More than 4096 tiles: the per-tile counts of threshold keys go through
+    the separate scan; ties spread over many tiles; the threshold key and the
+    kept count are exact."""
+    import torch
+
+    from paper_2606_09074_amd import api
+    rng = np.random.default_rng(5)
+    vals = (rng.integers(0, 3000, size=n) * np.float32(0.25)).astype(np.float32)   # heavy ties
+    n_prune = int(n * 0.37)
+    dev = torch.device("cuda:0")
+    s = torch.from_numpy(vals).to(dev)
+    keep = torch.empty(n, dtype=torch.uint8, device=dev)
+    nk = torch.empty(1, dtype=torch.int64, device=dev)
+    thr = torch.empty(1, dtype=torch.int32, device=dev)
+    ws = api.workspace(n, 1, dev)
+    log(f"select n={n} tiles={(n + 4095) // 4096}")
+    api.refine_select(s, keep, ws, n_prune=n_prune, n_keep_out=nk, threshold_out=thr)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(keep.cpu().numpy(), expected_keep_from_scores(vals, n_prune))
+    assert int(nk.item()) == n - n_prune
+
+
 @pytest.mark.parametrize("n_prune", [0, 1, 2, 4999, 5000])
 def test_select_edges_and_ties(n_prune):
     import torch
