@@ -27,22 +27,15 @@ constexpr float kShC0 = 0.28209479177387814f;   // real SH band-0 basis value 1/
 
 __device__ inline bool finite_bits(float f) { return (__float_as_uint(f) & 0x7f800000u) != 0x7f800000u; }
 
-template <int ST>
-__global__ __launch_bounds__(kBlock) void stats_partial(const void* __restrict__ planes, int64_t stride,
-                                                          int n, float eta, double* __restrict__ part)
-{
-    const int tile = blockIdx.x;
-    const int base = tile * kTile;
+// Per-thread accumulators of the tile: FP64 sums of the features, the
+// non-finite count and the box of the finite centres.
+struct Acc {
     double sY = 0.0, sY2 = 0.0, sOpa = 0.0, sGem = 0.0;
     uint32_t bad = 0;
     float bmin[3] = {INFINITY, INFINITY, INFINITY}, bmax[3] = {-INFINITY, -INFINITY, -INFINITY};
-#pragma unroll 4
-    for (int k = 0; k < kItems; ++k) {
-        const int i = base + k * kBlock + (int)threadIdx.x;
-        if (i >= n) break;
-        float v[kScorePlanes];
-#pragma unroll
-        for (int p = 0; p < kScorePlanes; ++p) v[p] = load_plane<ST>(planes, stride, p, i);
+
+    __device__ void add(const float (&v)[kScorePlanes], float eta)
+    {
         bool ok = true;
 #pragma unroll
         for (int p = 0; p < kScorePlanes; ++p) ok = ok && finite_bits(v[p]);
@@ -71,6 +64,15 @@ __global__ __launch_bounds__(kBlock) void stats_partial(const void* __restrict__
         sOpa += (double)amb;
         sGem += (double)gem;
     }
+};
+
+// Block reduction of the accumulators and the tile's partial record.
+__device__ void reduce_and_store(Acc& a, int tile, double* __restrict__ part)
+{
+    double sY = a.sY, sY2 = a.sY2, sOpa = a.sOpa, sGem = a.sGem;
+    uint32_t bad = a.bad;
+    float* bmin = a.bmin;
+    float* bmax = a.bmax;
     sY = wave_sum(sY);
     sY2 = wave_sum(sY2);
     sOpa = wave_sum(sOpa);
@@ -112,6 +114,26 @@ __global__ __launch_bounds__(kBlock) void stats_partial(const void* __restrict__
         const uint64_t bits = (uint64_t)__float_as_uint(lo) | ((uint64_t)__float_as_uint(hi) << 32);
         part[(int64_t)tile * kStatSlots + threadIdx.x] = __longlong_as_double((long long)bits);
     }
+}
+
+
+template <int ST>
+__global__ __launch_bounds__(kBlock) void stats_partial(const void* __restrict__ planes, int64_t stride,
+                                                          int n, float eta, double* __restrict__ part)
+{
+    const int tile = blockIdx.x;
+    const int base = tile * kTile;
+    Acc a;
+#pragma unroll 4
+    for (int k = 0; k < kItems; ++k) {
+        const int i = base + k * kBlock + (int)threadIdx.x;
+        if (i >= n) break;
+        float v[kScorePlanes];
+#pragma unroll
+        for (int p = 0; p < kScorePlanes; ++p) v[p] = load_plane<ST>(planes, stride, p, i);
+        a.add(v, eta);
+    }
+    reduce_and_store(a, tile, part);
 }
 
 __global__ __launch_bounds__(kBlock) void stats_finalize(const double* __restrict__ part, int ntiles, int64_t n,
