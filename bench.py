@@ -246,9 +246,10 @@ def main() -> int:
 
 
 def serve_bench(args) -> dict:
-    """Served latency: Poisson arrivals of prune jobs on resident scenes
-    (paper_2606_09074_amd.serve), once with FP32 scenes and once with the same
-    scenes in 2-byte storage, then a burst of the same jobs with and without
+    """Served latency: Poisson arrivals of prune jobs on resident, prepared
+    scenes (paper_2606_09074_amd.serve), once with FP32 scenes and once with
+    the same scenes in 2-byte storage, once more with FP32 scenes where every
+    job runs the whole path, then a burst of the same jobs with and without
     overlap.  Latency = completion seen by the host - arrival time."""
     import numpy as np
     import torch
@@ -274,8 +275,8 @@ def serve_bench(args) -> dict:
     tuner.tune(f32[-1], lambda V: torch.from_numpy(synth.ring_cameras(V)).to(dev), buckets, reps=3)
     log(f"serve: tuned {len(buckets)} buckets: {sorted(tuner.table.items())}")
 
-    def run(scenes, arr, slots):
-        srv = serve.Server(dev, slots=slots, tuner=tuner)
+    def run(scenes, arr, slots, prepare=True):
+        srv = serve.Server(dev, slots=slots, tuner=tuner, prepare_scenes=prepare)
         for t in scenes:
             srv.add_scene(t)
         # warm the allocator and the kernels on every scene
@@ -307,6 +308,8 @@ def serve_bench(args) -> dict:
     r32, k32 = run(f32, arrivals, args.serve_slots)
     log(f"serve: same jobs, BF16/FP16 scenes")
     r16, k16 = run(b16, arrivals, args.serve_slots)
+    log(f"serve: same jobs, FP32 scenes, every job on the whole path (no prepared scenes)")
+    r32u, _ = run(f32, arrivals, args.serve_slots, prepare=False)
     jac = []
     for a, b in zip(k32, k16):
         a, b = a.bool(), b.bool()
@@ -318,7 +321,7 @@ def serve_bench(args) -> dict:
     return {"workload": "resident scenes n=0.25M..4.9M (log-uniform strata), 50..300 ring views, ratio 0.3..0.9",
             "jobs": len(reqs), "rate_per_s": args.serve_rate, "slots": args.serve_slots,
             "latency_clock": "host: arrival to observed completion",
-            "f32": r32, "bf16_f16": r16,
+            "f32": r32, "bf16_f16": r16, "f32_whole_path": r32u,
             "kept_jaccard_bf16_vs_f32": {"min": round(min(jac), 5), "mean": round(float(np.mean(jac)), 5)},
             "burst": {"slots": args.serve_slots, "jobs_per_s": b4["jobs_per_s"], "evals_per_s": b4["evals_per_s"],
                       "one_slot_jobs_per_s": b1["jobs_per_s"]}}

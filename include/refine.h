@@ -167,8 +167,9 @@ void refine_params_default(refine_params* p);
 int64_t refine_prune_count(int64_t n, double ratio);
 
 /* Workspace bytes needed by every call below for scenes of up to n
- * primitives and n_views cameras.  REFINE_E_INVALID on negative sizes or a
- * NULL `bytes`. */
+ * primitives and n_views cameras; with n_views = 0, the (much smaller) size
+ * that refine_stats, refine_select and refine_compact need, which take no
+ * cameras.  REFINE_E_INVALID on negative sizes or a NULL `bytes`. */
 refine_status refine_workspace_size(int64_t n, int32_t n_views, size_t* bytes);
 
 /*
@@ -204,13 +205,21 @@ refine_status refine_score(const refine_scene* scene, const float* d_cams, int32
  *                        binned path, the spatially binned, activated copy of
  *                        the scene in the workspace.  It depends only on the
  *                        scene, the cameras, the parameters and d_stats.
+ *  refine_score_cameras  rebuilds only the per-view tables, for a new camera
+ *                        set (any n_views the workspace was sized for; the
+ *                        scene fixes the workspace layout, its planes are not
+ *                        read).  The binned copy of the scene does not
+ *                        depend on the cameras, so a scene prepared once can
+ *                        be scored for many camera sets: prepare once, then
+ *                        cameras + views per camera set, with the same scene,
+ *                        params and d_stats.
  *  refine_score_views    evaluates every (primitive, view) pair that can
  *                        contribute and writes d_scores.  It reads the tables
- *                        the last refine_score_prepare on the same workspace
- *                        built, so the same scene, n_views, params and d_stats
- *                        must be passed (scene->planes is read only on the
- *                        direct path).  Several views calls may follow one
- *                        prepare (e.g. the same scene scored repeatedly).
+ *                        the last prepare / cameras call on the same
+ *                        workspace built, so the same scene, n_views, params
+ *                        and d_stats must be passed (scene->planes is read
+ *                        only on the direct path).  Several views calls may
+ *                        follow one prepare.
  *  d_evaluated (nullable, device int64) receives the number of pairs the
  *  view loop evaluated in full (n * |V| on the direct path; on the binned
  *  path, pairs of 64-primitive groups whose bound reaches the view).
@@ -218,6 +227,8 @@ refine_status refine_score(const refine_scene* scene, const float* d_cams, int32
 refine_status refine_score_prepare(const refine_scene* scene, const float* d_cams, int32_t n_views,
                                    const refine_params* params, const refine_stats_t* d_stats,
                                    void* d_ws, size_t ws_bytes, void* stream);
+refine_status refine_score_cameras(const refine_scene* scene, const float* d_cams, int32_t n_views,
+                                   const refine_params* params, void* d_ws, size_t ws_bytes, void* stream);
 refine_status refine_score_views(const refine_scene* scene, int32_t n_views, const refine_params* params,
                                  const refine_stats_t* d_stats, float* d_scores, int64_t* d_evaluated,
                                  void* d_ws, size_t ws_bytes, void* stream);

@@ -24,7 +24,8 @@ VIS_ALPHA, VIS_NONE = 0, 1
 PATH_AUTO, PATH_DIRECT, PATH_BINNED = 0, 1, 2
 
 EXPORTED = ("refine_version", "refine_status_string", "refine_params_default", "refine_prune_count",
-            "refine_workspace_size", "refine_stats", "refine_score", "refine_score_prepare", "refine_score_views",
+            "refine_workspace_size", "refine_stats", "refine_score", "refine_score_prepare", "refine_score_cameras",
+            "refine_score_views",
             "refine_select", "refine_compact")
 
 

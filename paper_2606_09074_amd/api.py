@@ -19,7 +19,8 @@ from . import _lib
 from ._lib import Params, Scene, Stats, check, default_params
 
 __all__ = ["Params", "default_params", "workspace", "workspace_size", "prune_count", "refine_stats",
-           "refine_score", "refine_score_prepare", "refine_score_views", "refine_select", "refine_compact",
+           "refine_score", "refine_score_prepare", "refine_score_cameras", "refine_score_views", "refine_select",
+           "refine_compact",
            "stats_from_tensor", "prune", "version"]
 
 
@@ -117,6 +118,17 @@ def refine_score_prepare(planes: torch.Tensor, cams: torch.Tensor, stats: torch.
     check(_lib.load().refine_score_prepare(ctypes.byref(sc), _ptr(cams), cams.shape[0], ctypes.byref(params),
                                            _ptr(stats), _ptr(ws), ws.numel(), _stream_ptr(stream)),
           "refine_score_prepare")
+
+
+def refine_score_cameras(planes: torch.Tensor, cams: torch.Tensor, ws: torch.Tensor,
+                         params: Optional[Params] = None, n: Optional[int] = None, stream=None) -> None:
+    """Rebuild only the per-view tables in ``ws`` for a new camera set; the
+    binned scene copy from an earlier refine_score_prepare is kept."""
+    params = params or default_params()
+    sc = _scene(planes, n)
+    _check_cams(cams)
+    check(_lib.load().refine_score_cameras(ctypes.byref(sc), _ptr(cams), cams.shape[0], ctypes.byref(params),
+                                           _ptr(ws), ws.numel(), _stream_ptr(stream)), "refine_score_cameras")
 
 
 def refine_score_views(planes: torch.Tensor, n_views: int, stats: torch.Tensor, scores_out: torch.Tensor,

@@ -76,14 +76,17 @@ size_t workspace_layout(int64_t n, int32_t n_views, bool score, void* base, Work
     const size_t o_part = off;  off += align_up(sizeof(double) * kStatSlots * nt);
     const size_t o_cnt = off;   off += align_up(sizeof(uint32_t) * nt);
     const size_t o_toff = off;  off += align_up(sizeof(uint32_t) * nt);
-    // sections only refine_score uses come last, so the other calls need a prefix only
+    // sections only refine_score uses come after, so the other calls need a
+    // prefix only; the camera tables come last, so that no other section's
+    // place depends on the number of views (a workspace prepared for one
+    // camera set keeps its binned scene when the tables are rebuilt)
     const size_t o_eval = off;  off += score ? align_up(sizeof(unsigned long long) * kEvalSlots) : 0;
-    const size_t o_cams = off;  off += score ? align_up(sizeof(CamRec) * nv) : 0;
-    const size_t o_cull = off;  off += score ? align_up(sizeof(CullRec) * nv) : 0;
     const size_t o_ccnt = off;  off += score ? align_up(sizeof(uint32_t) * kCells) : 0;
     const size_t o_ccur = off;  off += score ? align_up(sizeof(uint32_t) * kCells) : 0;
     const size_t o_dest = off;  off += score ? align_up(sizeof(uint32_t) * (size_t)n) : 0;
     const size_t o_recs = off;  off += score ? align_up(sizeof(PrimRec) * (size_t)n) : 0;
+    const size_t o_cams = off;  off += score ? align_up(sizeof(CamRec) * nv) : 0;
+    const size_t o_cull = off;  off += score ? align_up(sizeof(CullRec) * nv) : 0;
     if (base && ws) {
         char* b = static_cast<char*>(base);
         ws->sel = reinterpret_cast<SelectState*>(b + o_sel);
@@ -151,7 +154,7 @@ refine_status refine_workspace_size(int64_t n, int32_t n_views, size_t* bytes)
 {
     if (!bytes || n < 0 || n_views < 0) return REFINE_E_INVALID;
     if (n > (int64_t)std::numeric_limits<int32_t>::max() || n_views > kMaxViews) return REFINE_E_UNSUPPORTED;
-    *bytes = workspace_layout(n, n_views, true, nullptr, nullptr);
+    *bytes = workspace_layout(n, n_views, n_views > 0, nullptr, nullptr);
     return REFINE_OK;
 }
 
@@ -195,6 +198,20 @@ refine_status refine_score_prepare(const refine_scene* scene, const float* d_cam
     if ((s = check_workspace(scene->n, n_views, true, d_ws, ws_bytes, &ws)) != REFINE_OK) return s;
     const hipError_t e = launch_score_prepare(scene->planes, storage_of(scene), scene->stride, scene->n, d_cams,
                                               n_views, *params, d_stats, ws, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? REFINE_OK : REFINE_E_HIP;
+}
+
+refine_status refine_score_cameras(const refine_scene* scene, const float* d_cams, int32_t n_views,
+                                   const refine_params* params, void* d_ws, size_t ws_bytes, void* stream)
+{
+    refine_status s = check_scene(scene);
+    if (s != REFINE_OK) return s;
+    if ((s = check_params(params)) != REFINE_OK) return s;
+    if (n_views < 1 || !d_cams) return REFINE_E_INVALID;
+    if (n_views > kMaxViews) return REFINE_E_UNSUPPORTED;
+    Workspace ws;
+    if ((s = check_workspace(scene->n, n_views, true, d_ws, ws_bytes, &ws)) != REFINE_OK) return s;
+    const hipError_t e = launch_score_cameras(d_cams, n_views, *params, ws, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? REFINE_OK : REFINE_E_HIP;
 }
 

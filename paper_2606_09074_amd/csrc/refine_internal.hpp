@@ -120,6 +120,8 @@ hipError_t launch_stats(const void* planes, int st, int64_t stride, int64_t n, c
 hipError_t launch_score_prepare(const void* planes, int st, int64_t stride, int64_t n, const float* d_cams,
                                 int32_t n_views, const refine_params& prm, const refine_stats_t* d_stats,
                                 const Workspace& ws, hipStream_t stream);
+hipError_t launch_score_cameras(const float* d_cams, int32_t n_views, const refine_params& prm, const Workspace& ws,
+                                hipStream_t stream);
 hipError_t launch_score_views(const void* planes, int st, int64_t stride, int64_t n, int32_t n_views,
                               const refine_params& prm, const refine_stats_t* d_stats, float* d_scores,
                               int64_t* d_evaluated, const Workspace& ws, hipStream_t stream);

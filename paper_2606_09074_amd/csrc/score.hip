@@ -25,7 +25,9 @@
 //   projection term: COV (a + c)/(z^2 + eta) (1/sbar^2 applied in the
 //       epilogue), DEPTH 1/(z^2 + eta) (Eq. 17), NONE 1
 // Views are accumulated in view order into one FP32 sum per primitive; the
-// epilogue forms D = V K S / |V| (Eq. 20, then Eq. 7).
+// epilogue forms D = (V K [/ sbar^2]) S / |V| (Eq. 20, then Eq. 7).  The
+// binned records hold V K [/ sbar^2], which does not depend on the cameras,
+// so a new camera set only needs new camera records (refine_score_cameras).
 //
 // Direct path (score_direct): one primitive per lane in input order, every
 // pair evaluated.
@@ -141,7 +143,7 @@ static_assert(offsetof(CamRec, hh) + sizeof(float) <= kStageVec * sizeof(float4)
 // Activation (Sec. 3.1 readings) of primitive i; pre is the epilogue factor.
 template <int ST>
 __device__ inline void activate(const void* __restrict__ planes, int64_t stride, int i, Prim& p, float& pre,
-                                float& smax, const refine_stats_t* __restrict__ st, int proj, int vis_alpha, int nv)
+                                float& smax, const refine_stats_t* __restrict__ st, int proj, int vis_alpha)
 {
     float a[kScorePlanes];
 #pragma unroll
@@ -176,7 +178,7 @@ __device__ inline void activate(const void* __restrict__ planes, int64_t stride,
     const float g_gem = fmaxf(s0 * s1, fmaxf(s0 * s2, s1 * s2));
     const float g_col = sqrtf(cr * cr + cg * cg + cb * cb);
     const float K = (float)st->lambda[0] * g_gem + (float)st->lambda[1] * g_col + (float)st->lambda[2] * alpha;
-    pre = (vis_alpha ? alpha : 1.0f) * K / (float)nv;
+    pre = (vis_alpha ? alpha : 1.0f) * K;
     if (proj == REFINE_PROJ_COV) pre = pre / sbar2;
 }
 
@@ -237,9 +239,9 @@ __global__ __launch_bounds__(kBlock) void score_direct(const void* __restrict__ 
     if (i >= n) return;
     Prim p;
     float pre, smax;
-    activate<ST>(planes, stride, i, p, pre, smax, st, PROJ, vis_alpha, nv);
+    activate<ST>(planes, stride, i, p, pre, smax, st, PROJ, vis_alpha);
     for (int v = 0; v < nv; ++v) eval_pair<PROJ>(cams[v], p, eta, z_near);
-    out[i] = pre * p.S;
+    out[i] = pre * p.S / (float)nv;
 }
 
 // ------------------------------------------------------------- binned path
@@ -357,14 +359,14 @@ __global__ __launch_bounds__(kBlock) void bin_rank(const void* __restrict__ plan
 // Activated primitives written as records at their binned positions.
 template <int PROJ, int ST>
 __global__ __launch_bounds__(kBlock) void bin_scatter(const void* __restrict__ planes, int64_t stride, int n,
-                                                        const refine_stats_t* __restrict__ st, int vis_alpha, int nv,
+                                                        const refine_stats_t* __restrict__ st, int vis_alpha,
                                                         const uint32_t* __restrict__ dest, PrimRec* __restrict__ recs)
 {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     Prim p;
     float pre, smax;
-    activate<ST>(planes, stride, i, p, pre, smax, st, PROJ, vis_alpha, nv);
+    activate<ST>(planes, stride, i, p, pre, smax, st, PROJ, vis_alpha);
     const uint32_t pos = dest[i];
     PrimRec r;
     r.mu[0] = p.mx; r.mu[1] = p.my; r.mu[2] = p.mz;
@@ -508,7 +510,7 @@ __global__ __launch_bounds__(kBlock) void score_binned(const PrimRec* __restrict
     }
 #pragma unroll
     for (int k = 0; k < PPL; ++k)
-        if (idx[k] >= 0) out[idx[k]] = pre[k] * p[k].S;
+        if (idx[k] >= 0) out[idx[k]] = pre[k] * p[k].S / (float)nv;
     if (evaluated && lane == 0) {
         const int valid = max(0, min(64 * PPL, n - g0));   // records of this group
         const int slot = (g0 / (64 * PPL)) % kEvalSlots;   // spread: one address would serialise the waves
@@ -530,7 +532,7 @@ __global__ void counter_store(const unsigned long long* c, int64_t* out, int64_t
 
 template <int PROJ, int ST>
 void prepare_mode(const void* planes, int64_t stride, int n, const refine_params& prm, const refine_stats_t* d_stats,
-                  const Workspace& ws, int nv, hipStream_t stream)
+                  const Workspace& ws, hipStream_t stream)
 {
     const int vis = prm.vis_mode == REFINE_VIS_ALPHA ? 1 : 0;
     const dim3 grid((unsigned)((n + kBlock - 1) / kBlock));
@@ -539,7 +541,7 @@ void prepare_mode(const void* planes, int64_t stride, int n, const refine_params
     hipLaunchKernelGGL(bin_scan, dim3(1), dim3(kScanThreads), 0, stream, ws.cell_cnt, ws.cell_cur);
     hipLaunchKernelGGL(bin_rank<ST>, tiles, dim3(kBlock), 0, stream, planes, stride, n, d_stats, ws.cell_cur,
                        ws.dest);
-    hipLaunchKernelGGL((bin_scatter<PROJ, ST>), grid, dim3(kBlock), 0, stream, planes, stride, n, d_stats, vis, nv, ws.dest,
+    hipLaunchKernelGGL((bin_scatter<PROJ, ST>), grid, dim3(kBlock), 0, stream, planes, stride, n, d_stats, vis, ws.dest,
                        ws.recs);
 }
 
@@ -606,9 +608,17 @@ hipError_t launch_score_prepare(const void* planes, int st, int64_t stride, int6
                        (float)prm.clamp_k, ws.cams, ws.culls, binned ? ws.cell_cnt : nullptr);
     if (!binned) return hipGetLastError();
     dispatch_mode(prm.proj_mode, st, [&](auto proj_c, auto st_c) {
-        prepare_mode<decltype(proj_c)::value, decltype(st_c)::value>(planes, stride, (int)n, prm, d_stats, ws, nv,
-                                                                     stream);
+        prepare_mode<decltype(proj_c)::value, decltype(st_c)::value>(planes, stride, (int)n, prm, d_stats, ws, stream);
     });
+    return hipGetLastError();
+}
+
+hipError_t launch_score_cameras(const float* d_cams, int32_t n_views, const refine_params& prm, const Workspace& ws,
+                                hipStream_t stream)
+{
+    const int nv = views_of(prm, n_views);
+    hipLaunchKernelGGL(camera_prep, dim3((nv + kBlock - 1) / kBlock), dim3(kBlock), 0, stream, d_cams, n_views, nv,
+                       (float)prm.clamp_k, ws.cams, ws.culls, nullptr);
     return hipGetLastError();
 }
 

@@ -5,16 +5,24 @@ bottom beta * N) of a scene that stays resident in device memory, seen
 from the job's own camera set.  The server
 
 * keeps scenes resident (``add_scene``), each plane padded to a multiple of
-  8 elements so the library's 16-byte-load kernels apply, and takes jobs as
-  they arrive (``submit``), in arrival order;
+  8 elements so the library's 16-byte-load kernels apply, together with what
+  scoring needs of the scene alone: its statistics and its spatially binned,
+  activated copy (``refine_score_prepare``), which do not depend on the
+  cameras -- a job then only rebuilds the camera tables
+  (``refine_score_cameras``) before the view loop;
+* takes jobs as they arrive (``submit``), in arrival order;
 * admits the head of the queue as soon as an in-flight slot and enough
   device memory are free: a job reserves its workspace, scores, mask,
   survivor planes and index map (``job_bytes``) against a budget, which by
   default is the device's memory less the resident scenes and a reserve;
-* runs every admitted job's five library calls (stats, score prepare,
-  view loop, select, compact) on that slot's own HIP stream, so jobs that
-  arrive while others run overlap on the device -- a small scene does not
-  fill the 256 compute units, and its launches interleave with the others';
+* runs an admitted job's camera tables and view loop on its scene's stream
+  (they write the scene's prepared workspace, so jobs on one scene take
+  their turns there) and its selection and compaction on the slot's own HIP
+  stream, with its own small workspace; jobs that arrive while others run
+  overlap on the device -- a small scene does not fill the 256 compute
+  units, and its launches interleave with the others'.  Jobs with their own
+  parameters, or more views than a scene was prepared for, run the whole
+  path (stats, prepare, views, select, compact) on the slot's stream;
 * notices completions by polling an event recorded after each job's last
   call, then frees the slot and the reservation and admits the next jobs.
 
@@ -178,6 +186,7 @@ class Job:
     n: int = 0
     n_keep: int = 0
     nbytes: int = 0
+    on_prepared: bool = False     # scored on its scene's prepared workspace
     t_admit: float = 0.0
     t_done: float = 0.0
     slot: int = -1
@@ -205,7 +214,8 @@ class Server:
     """Continuous-batching prune server on one device (see module doc)."""
 
     def __init__(self, device="cuda:0", slots: int = 4, budget_bytes: Optional[int] = None,
-                 reserve_bytes: int = 8 << 30, tuner: Optional[Tuner] = None):
+                 reserve_bytes: int = 8 << 30, tuner: Optional[Tuner] = None, prepare_scenes: bool = True,
+                 max_views: int = 512):
         import torch
 
         from . import _lib
@@ -216,6 +226,9 @@ class Server:
         self.free_slots = collections.deque(range(slots))
         self.scenes: dict[int, object] = {}      # id -> padded [59, stride] tensor
         self.scene_n: dict[int, int] = {}
+        self.prepared: dict[int, tuple] = {}      # id -> (stats, workspace, stream)
+        self.max_views = int(max_views)
+        self.prepare_scenes = bool(prepare_scenes)
         self.scene_bytes = 0
         self.reserve = int(reserve_bytes)
         self.explicit_budget = budget_bytes
@@ -250,9 +263,35 @@ class Server:
         self.scenes[sid] = planes
         self.scene_n[sid] = n
         self.scene_bytes += planes.numel() * planes.element_size()
+        if self.prepare_scenes and n > 0:
+            self._prepare(sid)
         if self.explicit_budget is None:
             self.admission.budget = self._budget()
         return sid
+
+    def _prepare(self, sid: int) -> None:
+        """Statistics and the binned copy of scene `sid` with the default
+        parameters, in a workspace sized for max_views cameras."""
+        from . import _lib, api
+        torch = self.torch
+        planes, n = self.scenes[sid], self.scene_n[sid]
+        prm = _lib.default_params()
+        prm.score_path = _lib.PATH_BINNED
+        s = torch.cuda.Stream(self.device)
+        ws = api.workspace(n, self.max_views, self.device)
+        st = torch.empty(_lib.STATS_BYTES, dtype=torch.uint8, device=self.device)
+        one_cam = torch.zeros((1, 18), dtype=torch.float32, device=self.device)
+        one_cam[0, 0] = one_cam[0, 4] = one_cam[0, 8] = 1.0
+        one_cam[0, 11] = 1.0
+        one_cam[0, 12:18] = torch.tensor([1.0, 1.0, 0.5, 0.5, 1.0, 1.0])
+        s.wait_stream(torch.cuda.current_stream(self.device))
+        api.refine_stats(planes, st, ws, prm, n=n, stream=s)
+        api.refine_score_prepare(planes, one_cam, st, ws, prm, n=n, stream=s)
+        s.synchronize()
+        self.prepared[sid] = (st, ws, s)
+        self.scene_bytes += ws.numel()
+        if self.explicit_budget is None:
+            self.admission.budget = self._budget()
 
     # jobs -----------------------------------------------------------------
     def submit(self, scene: int, cams, ratio: float, params=None, t_arrival: Optional[float] = None) -> Job:
@@ -270,7 +309,9 @@ class Server:
         n_keep = n - api.prune_count(n, ratio)
         job = Job(self._next_id, scene, cams, float(ratio), prm,
                   time.perf_counter() if t_arrival is None else t_arrival, n=n, n_keep=n_keep)
-        job.nbytes = job_bytes(n, V, n_keep, planes.element_size(), api.workspace_size(n, V))
+        job.on_prepared = params is None and scene in self.prepared and V <= self.max_views
+        job.nbytes = job_bytes(n, V, n_keep, planes.element_size(),
+                               api.workspace_size(n, 0 if job.on_prepared else V))
         if not self.admission.fits_ever(job.nbytes):
             raise ValueError(f"job needs {job.nbytes} bytes, more than the budget {self.admission.budget}")
         self._next_id += 1
@@ -286,7 +327,7 @@ class Server:
         n, V = job.n, job.cams.shape[0]
         dev = self.device
         with torch.cuda.stream(s):
-            job.workspace = api.workspace(n, V, dev)
+            job.workspace = api.workspace(n, 0 if job.on_prepared else V, dev)
             job.stats = torch.empty(_lib.STATS_BYTES, dtype=torch.uint8, device=dev)
             job.scores = torch.empty(max(n, 1), dtype=torch.float32, device=dev)
             job.keep = torch.empty(max(n, 1), dtype=torch.uint8, device=dev)
@@ -294,12 +335,24 @@ class Server:
             job.out = torch.empty((N_PLANES, out_stride), dtype=planes.dtype, device=dev)
             job.index_map = torch.empty(max(job.n_keep, 1), dtype=torch.int32, device=dev)
             job.n_out = torch.empty(1, dtype=torch.int64, device=dev)
-        # the camera table may have been written on another stream
-        s.wait_stream(torch.cuda.current_stream(dev))
         job.start_event = torch.cuda.Event(enable_timing=True)
-        job.start_event.record(s)
-        api.refine_stats(planes, job.stats, job.workspace, job.params, n=n, stream=s)
-        api.refine_score(planes, job.cams, job.stats, job.scores, job.workspace, job.params, n=n, stream=s)
+        if job.on_prepared:
+            st, pws, ss = self.prepared[job.scene]
+            # the camera table may have been written on another stream
+            ss.wait_stream(torch.cuda.current_stream(dev))
+            ss.wait_stream(s)          # this slot's previous job no longer reads its buffers
+            job.start_event.record(ss)
+            job.stats = st
+            api.refine_score_cameras(planes, job.cams, pws, job.params, n=n, stream=ss)
+            api.refine_score_views(planes, V, st, job.scores, pws, job.params, n=n, stream=ss)
+            scored = torch.cuda.Event()
+            scored.record(ss)
+            s.wait_event(scored)
+        else:
+            s.wait_stream(torch.cuda.current_stream(dev))
+            job.start_event.record(s)
+            api.refine_stats(planes, job.stats, job.workspace, job.params, n=n, stream=s)
+            api.refine_score(planes, job.cams, job.stats, job.scores, job.workspace, job.params, n=n, stream=s)
         api.refine_select(job.scores, job.keep, job.workspace, ratio=job.ratio, n=n, stream=s)
         api.refine_compact(planes, job.keep, job.out, job.workspace, index_map_out=job.index_map,
                            n_out=job.n_out, n=n, capacity=job.n_keep, stream=s)

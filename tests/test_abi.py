@@ -78,6 +78,9 @@ def test_workspace_size(lib):
     assert lib.refine_workspace_size(10, -1, ctypes.byref(sz)) == _lib.REFINE_E_INVALID
     assert lib.refine_workspace_size(1 << 31, 16, ctypes.byref(sz)) == _lib.REFINE_E_UNSUPPORTED
     assert lib.refine_workspace_size(10, 16, None) == _lib.REFINE_E_INVALID
+    # no cameras: only what stats, select and compact use (no binned scene copy)
+    assert lib.refine_workspace_size(3_000_000, 0, ctypes.byref(sz)) == 0
+    assert 0 < sz.value < big // 50
 
 
 FAKE = 0x10000   # never dereferenced: every call below fails validation first
@@ -151,6 +154,20 @@ def test_two_phase_validation(lib):
     assert lib.refine_score_views(ctypes.byref(sc), 16, ctypes.byref(p), FAKE, None, None, FAKE, 1 << 30, None) == E
     assert lib.refine_score_views(ctypes.byref(sc), -1, ctypes.byref(p), FAKE, FAKE, None, FAKE, 1 << 30, None) == E
     assert lib.refine_score_views(ctypes.byref(sc), 16, None, FAKE, FAKE, None, FAKE, 1 << 30, None) == E
+    cams = lib.refine_score_cameras
+    assert cams(None, FAKE, 16, ctypes.byref(p), FAKE, 1 << 30, None) == E
+    assert cams(ctypes.byref(sc), None, 16, ctypes.byref(p), FAKE, 1 << 30, None) == E
+    assert cams(ctypes.byref(sc), FAKE, 0, ctypes.byref(p), FAKE, 1 << 30, None) == E
+    assert cams(ctypes.byref(sc), FAKE, 16, None, FAKE, 1 << 30, None) == E
+    assert cams(ctypes.byref(sc), FAKE, 16, ctypes.byref(p), FAKE, 64, None) == _lib.REFINE_E_WORKSPACE
+    assert cams(ctypes.byref(sc), FAKE, 16, ctypes.byref(p), None, 1 << 30, None) == _lib.REFINE_E_WORKSPACE
+    # a workspace sized for 16 views has no room for the tables of 17
+    need = ctypes.c_size_t(0)
+    assert lib.refine_workspace_size(100, 16, ctypes.byref(need)) == 0
+    big = ctypes.c_size_t(0)
+    assert lib.refine_workspace_size(100, 17, ctypes.byref(big)) == 0
+    if big.value > need.value:
+        assert cams(ctypes.byref(sc), FAKE, 17, ctypes.byref(p), FAKE, need.value, None) == _lib.REFINE_E_WORKSPACE
 
 
 def test_select_validation(lib):

@@ -389,3 +389,38 @@ def test_compact_vector_and_scalar_kernels(n, stride, mask_offset, cap_frac):
     np.testing.assert_array_equal(o[:, :cap].view(np.uint32), planes[:, sel[:cap]].view(np.uint32))
     np.testing.assert_array_equal(idx.cpu().numpy()[:cap], sel[:cap])
     assert np.all(np.isnan(o[:, cap:])) and np.all(idx.cpu().numpy()[cap:] == -7)
+
+
+@pytest.mark.parametrize("path,rec", [(1, 0), (2, 1), (2, 2)])
+def test_rescoring_with_new_cameras(path, rec):
+    """A scene prepared once and scored for further camera sets (camera tables
+    rebuilt only) gives the same scores, bit for bit, as scoring each camera
+    set from scratch; and those match the oracle."""
+    import torch
+
+    from paper_2606_09074_amd import _lib, api, synth
+    planes, camsA, spec = workload("small")
+    camsB = synth.ring_cameras(7)                       # fewer views, another rig
+    camsC = np.ascontiguousarray(camsA[::-1][:13])
+    dev = torch.device("cuda:0")
+    pl = torch.from_numpy(planes).to(dev)
+    prm = gpu_params(score_path=path, records_per_lane=rec)
+    ws = api.workspace(spec.n, 16, dev)
+    st = torch.empty(_lib.STATS_BYTES, dtype=torch.uint8, device=dev)
+    api.refine_stats(pl, st, ws, prm)
+    out = {}
+    tA = torch.from_numpy(camsA).to(dev)
+    api.refine_score_prepare(pl, tA, st, ws, prm)
+    for name, c in (("A", camsA), ("B", camsB), ("C", camsC), ("A2", camsA)):
+        tc = torch.from_numpy(c).to(dev)
+        if name != "A":
+            api.refine_score_cameras(pl, tc, ws, prm)
+        sc = torch.empty(spec.n, dtype=torch.float32, device=dev)
+        api.refine_score_views(pl, c.shape[0], st, sc, ws, prm)
+        out[name] = sc.cpu().numpy()
+    for name, c in (("A", camsA), ("B", camsB), ("C", camsC)):
+        fresh = run_gpu(planes, c, params=gpu_params(score_path=path, records_per_lane=rec))["scores"]
+        np.testing.assert_array_equal(out[name].view(np.uint32), fresh.view(np.uint32))
+        F, lam, D, lo, hi = oracle_all(planes, c)
+        check_scores(out[name], D, lo, hi, f"rescored {name} path={path} ppl={rec}")
+    np.testing.assert_array_equal(out["A2"].view(np.uint32), out["A"].view(np.uint32))

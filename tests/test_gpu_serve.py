@@ -49,17 +49,21 @@ def _server(scenes, **kw):
 
 
 def test_results_same_alone_and_in_the_mix(pool):
+    """Alone: one slot, every job on the whole path (stats, prepare, views,
+    select, compact).  In the mix: four slots, scenes prepared once, jobs
+    only rebuild camera tables; results must be identical."""
     scenes, jobs, cams = pool
-    # alone: one slot, one job at a time
     alone = []
-    srv1 = _server(scenes, slots=1)
+    srv1 = _server(scenes, slots=1, prepare_scenes=False)
+    srv1_jobs = []
     for sc, V, r in jobs:
-        srv1.submit(sc, cams[V], r)
+        srv1_jobs.append(srv1.submit(sc, cams[V], r))
         (job,) = srv1.drain()
         alone.append(_results(job))
     # in the mix: everything submitted at once, four jobs in flight
     srv4 = _server(scenes, slots=4)
     subm = [srv4.submit(sc, cams[V], r) for sc, V, r in jobs]
+    assert all(j.on_prepared for j in subm) and not any(j.on_prepared for j in srv1_jobs)
     peak = 0
     finished = []
     while not srv4.idle():
