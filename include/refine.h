@@ -266,6 +266,48 @@ refine_status refine_compact(const refine_scene* in, const uint8_t* d_keep, cons
                              int32_t* d_index_map, int64_t* d_n_out, void* d_ws, size_t ws_bytes,
                              void* stream);
 
+/*
+ * Batched pruning of many (small) scenes in one grouped launch per kernel:
+ * for every job, refine_stats, then refine_score evaluating every pair (the
+ * direct path: params->score_path and records_per_lane are not used; the
+ * scores equal refine_score's bit for bit), refine_select at the job's ratio
+ * and refine_compact -- the same results as those calls made job by job,
+ * with 13 launches for the whole batch instead of ~15 per job.  For serving
+ * loops that gather the small scenes that arrive together.
+ *  jobs       host array of n_jobs descriptions, read during the call (the
+ *             table is copied into the workspace with a host-to-device copy
+ *             on `stream`); 1 <= n_jobs <= 4096
+ *  scene      input scene, 1 <= scene.n <= 16,777,216 (4096 tiles)
+ *  d_cams     device [n_views][18] as for refine_score; n_views >= 1
+ *  ratio      prune ratio in (0, 1), as for refine_select
+ *  d_stats, d_scores, d_keep    device outputs as for refine_stats,
+ *             refine_score and refine_select; d_n_keep nullable
+ *  out        survivors as for refine_compact (out.n = capacity, same dtypes
+ *             as scene, no overlap with it); d_index_map, d_n_out nullable
+ *  params     shared by all jobs
+ * The workspace size comes from refine_prune_batch_workspace_size for the
+ * same jobs (it depends on each job's n and n_views).
+ */
+typedef struct {
+    refine_scene scene;
+    const float* d_cams;
+    int32_t n_views;
+    int32_t reserved;            /* must be 0 */
+    double ratio;
+    refine_stats_t* d_stats;
+    float* d_scores;
+    uint8_t* d_keep;
+    int64_t* d_n_keep;
+    refine_scene out;
+    int32_t* d_index_map;
+    int64_t* d_n_out;
+} refine_prune_job;
+
+refine_status refine_prune_batch_workspace_size(const refine_prune_job* jobs, int32_t n_jobs,
+                                                const refine_params* params, size_t* bytes);
+refine_status refine_prune_batch(const refine_prune_job* jobs, int32_t n_jobs, const refine_params* params,
+                                 void* d_ws, size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -26,7 +26,7 @@ PATH_AUTO, PATH_DIRECT, PATH_BINNED = 0, 1, 2
 EXPORTED = ("refine_version", "refine_status_string", "refine_params_default", "refine_prune_count",
             "refine_workspace_size", "refine_stats", "refine_score", "refine_score_prepare", "refine_score_cameras",
             "refine_score_views",
-            "refine_select", "refine_compact")
+            "refine_select", "refine_compact", "refine_prune_batch_workspace_size", "refine_prune_batch")
 
 
 class Scene(ctypes.Structure):
@@ -50,6 +50,13 @@ class Stats(ctypes.Structure):
 
 
 STATS_BYTES = ctypes.sizeof(Stats)
+
+
+class PruneJob(ctypes.Structure):
+    _fields_ = [("scene", Scene), ("cams", ctypes.c_void_p), ("n_views", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("ratio", ctypes.c_double), ("stats", ctypes.c_void_p),
+                ("scores", ctypes.c_void_p), ("keep", ctypes.c_void_p), ("n_keep", ctypes.c_void_p),
+                ("out", Scene), ("index_map", ctypes.c_void_p), ("n_out", ctypes.c_void_p)]
 
 _lib = None
 

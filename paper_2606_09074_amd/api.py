@@ -21,7 +21,7 @@ from ._lib import Params, Scene, Stats, check, default_params
 __all__ = ["Params", "default_params", "workspace", "workspace_size", "prune_count", "refine_stats",
            "refine_score", "refine_score_prepare", "refine_score_cameras", "refine_score_views", "refine_select",
            "refine_compact",
-           "stats_from_tensor", "prune", "version"]
+           "refine_prune_batch", "stats_from_tensor", "prune", "prune_batch", "version"]
 
 
 def version() -> str:
@@ -198,3 +198,63 @@ def prune(planes: torch.Tensor, cams: torch.Tensor, ratio: float, params: Option
     refine_compact(planes, keep, out, ws, index_map_out=idx, capacity=cap, stream=stream)
     return {"stats": st, "scores": scores, "keep": keep, "out": out[:, :cap], "index_map": idx[:cap],
             "n_keep": n_keep}
+
+
+def _batch_jobs(jobs) -> "ctypes.Array":
+    arr = (_lib.PruneJob * len(jobs))()
+    for k, j in enumerate(jobs):
+        _check_cams(j["cams"])
+        n = j.get("n")
+        arr[k].scene = _scene(j["planes"], n)
+        arr[k].cams = j["cams"].data_ptr()
+        arr[k].n_views = j["cams"].shape[0]
+        arr[k].reserved = 0
+        arr[k].ratio = float(j["ratio"])
+        arr[k].stats = j["stats"].data_ptr()
+        arr[k].scores = j["scores"].data_ptr()
+        arr[k].keep = j["keep"].data_ptr()
+        arr[k].n_keep = j["n_keep"].data_ptr() if j.get("n_keep") is not None else None
+        arr[k].out = _scene(j["out"], j.get("capacity"))
+        arr[k].index_map = j["index_map"].data_ptr() if j.get("index_map") is not None else None
+        arr[k].n_out = j["n_out"].data_ptr() if j.get("n_out") is not None else None
+    return arr
+
+
+def batch_workspace_size(jobs, params: Optional[Params] = None) -> int:
+    arr = _batch_jobs(jobs)
+    out = ctypes.c_size_t(0)
+    check(_lib.load().refine_prune_batch_workspace_size(arr, len(jobs), ctypes.byref(params or default_params()),
+                                                        ctypes.byref(out)), "refine_prune_batch_workspace_size")
+    return int(out.value)
+
+
+def refine_prune_batch(jobs, ws: torch.Tensor, params: Optional[Params] = None, stream=None) -> None:
+    """Enqueue the batched prune of ``jobs`` (dicts of tensors: planes, cams,
+    ratio, stats, scores, keep, out, optional n, n_keep, capacity, index_map,
+    n_out) in one grouped launch per kernel."""
+    arr = _batch_jobs(jobs)
+    check(_lib.load().refine_prune_batch(arr, len(jobs), ctypes.byref(params or default_params()), _ptr(ws),
+                                         ws.numel(), _stream_ptr(stream)), "refine_prune_batch")
+
+
+def prune_batch(scenes, cams, ratios, params: Optional[Params] = None, stream=None) -> list:
+    """Allocate the outputs and prune several resident scenes in one batch;
+    returns one dict of device tensors per scene (as ``prune``)."""
+    jobs = []
+    for planes, c, r in zip(scenes, cams, ratios):
+        n = planes.shape[1]
+        dev = planes.device
+        cap = n - prune_count(n, r)
+        jobs.append({"planes": planes, "cams": c, "ratio": r,
+                     "stats": torch.empty(_lib.STATS_BYTES, dtype=torch.uint8, device=dev),
+                     "scores": torch.empty(n, dtype=torch.float32, device=dev),
+                     "keep": torch.empty(n, dtype=torch.uint8, device=dev),
+                     "n_keep": torch.empty(1, dtype=torch.int64, device=dev),
+                     "out": torch.empty((59, max(cap, 1)), dtype=planes.dtype, device=dev), "capacity": cap,
+                     "index_map": torch.empty(max(cap, 1), dtype=torch.int32, device=dev),
+                     "n_out": torch.empty(1, dtype=torch.int64, device=dev)})
+    ws = torch.empty(max(batch_workspace_size(jobs, params), 1), dtype=torch.uint8, device=scenes[0].device)
+    refine_prune_batch(jobs, ws, params, stream)
+    for j in jobs:
+        j["workspace"] = ws
+    return jobs

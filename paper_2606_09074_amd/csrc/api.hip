@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstring>
 #include <limits>
+#include <vector>
 
 #include "refine_internal.hpp"
 
@@ -108,6 +109,59 @@ size_t workspace_layout(int64_t n, int32_t n_views, bool score, void* base, Work
 }  // namespace refine
 
 using namespace refine;
+
+namespace {
+
+constexpr int32_t kMaxBatchJobs = 4096;
+
+// Bytes of one job's workspace slice: selection state and histograms, tile
+// partials and counts, camera records.
+size_t batch_job_bytes(int64_t n, int32_t nv)
+{
+    const size_t nt = (size_t)num_tiles(n);
+    return align_up(sizeof(SelectState)) + align_up(sizeof(uint32_t) * kSelectHistWords) +
+           align_up(sizeof(double) * kStatSlots * nt) + align_up(sizeof(uint32_t) * nt) + align_up(sizeof(CamRec) * nv);
+}
+
+refine_status check_batch_job(const refine_prune_job& j)
+{
+    refine_status s = check_scene(&j.scene);
+    if (s != REFINE_OK) return s;
+    if ((s = check_scene(&j.out)) != REFINE_OK) return s;
+    if (j.scene.n < 1 || j.reserved != 0) return REFINE_E_INVALID;
+    if (num_tiles(j.scene.n) > kPrefixTilesMax) return REFINE_E_UNSUPPORTED;
+    if (j.scene.dtype != j.out.dtype || j.scene.sh_dtype != j.out.sh_dtype) return REFINE_E_INVALID;
+    if (!j.d_cams || j.n_views < 1) return REFINE_E_INVALID;
+    if (j.n_views > kMaxViews) return REFINE_E_UNSUPPORTED;
+    if (refine_prune_count(j.scene.n, j.ratio) < 0) return REFINE_E_INVALID;
+    if (!j.d_stats || !j.d_scores || !j.d_keep) return REFINE_E_INVALID;
+    const size_t es = storage_bytes(storage_of(&j.scene));
+    if (j.out.n > 0) {
+        const char* a0 = static_cast<const char*>(j.scene.planes);
+        const char* a1 = a0 + (size_t)kPlanes * (size_t)j.scene.stride * es;
+        const char* b0 = static_cast<const char*>(j.out.planes);
+        const char* b1 = b0 + (size_t)kPlanes * (size_t)j.out.stride * es;
+        if (a0 < b1 && b0 < a1) return REFINE_E_INVALID;
+    }
+    return REFINE_OK;
+}
+
+refine_status batch_size(const refine_prune_job* jobs, int32_t n_jobs, const refine_params* params, size_t* bytes)
+{
+    if (!jobs || !bytes || n_jobs < 1) return REFINE_E_INVALID;
+    if (n_jobs > kMaxBatchJobs) return REFINE_E_UNSUPPORTED;
+    refine_status s = check_params(params);
+    if (s != REFINE_OK) return s;
+    size_t total = align_up(sizeof(BatchJob) * (size_t)n_jobs);
+    for (int32_t k = 0; k < n_jobs; ++k) {
+        if ((s = check_batch_job(jobs[k])) != REFINE_OK) return s;
+        total += batch_job_bytes(jobs[k].scene.n, views_of(*params, jobs[k].n_views));
+    }
+    *bytes = total;
+    return REFINE_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -287,6 +341,81 @@ refine_status refine_compact(const refine_scene* in, const uint8_t* d_keep, cons
                                         out->stride, out->n, d_index_map, d_n_out, ws,
                                         static_cast<hipStream_t>(stream));
     return e == hipSuccess ? REFINE_OK : REFINE_E_HIP;
+}
+
+refine_status refine_prune_batch_workspace_size(const refine_prune_job* jobs, int32_t n_jobs,
+                                                const refine_params* params, size_t* bytes)
+{
+    return batch_size(jobs, n_jobs, params, bytes);
+}
+
+refine_status refine_prune_batch(const refine_prune_job* jobs, int32_t n_jobs, const refine_params* params,
+                                 void* d_ws, size_t ws_bytes, void* stream)
+{
+    size_t need = 0;
+    refine_status s = batch_size(jobs, n_jobs, params, &need);
+    if (s != REFINE_OK) return s;
+    if (!d_ws || ws_bytes < need) return REFINE_E_WORKSPACE;
+    char* base = static_cast<char*>(d_ws);
+    BatchJob* d_table = reinterpret_cast<BatchJob*>(base);
+    size_t off = align_up(sizeof(BatchJob) * (size_t)n_jobs);
+    std::vector<BatchJob> table((size_t)n_jobs);
+    int64_t tiles = 0, blocks = 0;
+    for (int32_t k = 0; k < n_jobs; ++k) {
+        const refine_prune_job& j = jobs[k];
+        BatchJob& b = table[(size_t)k];
+        std::memset(&b, 0, sizeof(b));
+        const int64_t n = j.scene.n;
+        const int nv = views_of(*params, j.n_views);
+        const int st = storage_of(&j.scene);
+        const size_t es = storage_bytes(st);
+        b.planes = j.scene.planes;
+        b.stride = j.scene.stride;
+        b.n = (int32_t)n;
+        b.st = st;
+        b.cams = j.d_cams;
+        b.n_views = j.n_views;
+        b.nv = nv;
+        b.stats = j.d_stats;
+        b.scores = j.d_scores;
+        b.keep = j.d_keep;
+        b.n_prune = refine_prune_count(n, j.ratio);
+        b.n_keep_out = j.d_n_keep;
+        b.out = j.out.planes;
+        b.out_stride = j.out.stride;
+        b.capacity = j.out.n;
+        b.index_map = j.d_index_map;
+        b.n_out = j.d_n_out;
+        const size_t nt = (size_t)num_tiles(n);
+        b.sel = reinterpret_cast<SelectState*>(base + off);
+        off += align_up(sizeof(SelectState));
+        b.hist = reinterpret_cast<uint32_t*>(base + off);
+        off += align_up(sizeof(uint32_t) * kSelectHistWords);
+        b.stat_part = reinterpret_cast<double*>(base + off);
+        off += align_up(sizeof(double) * kStatSlots * nt);
+        b.tile_cnt = reinterpret_cast<uint32_t*>(base + off);
+        off += align_up(sizeof(uint32_t) * nt);
+        b.cam_rec = reinterpret_cast<CamRec*>(base + off);
+        off += align_up(sizeof(CamRec) * (size_t)nv);
+        b.tile0 = (int32_t)tiles;
+        b.block0 = (int32_t)blocks;
+        tiles += (int64_t)nt;
+        blocks += (n + kBlock - 1) / kBlock;
+        b.vec_compact = (reinterpret_cast<uintptr_t>(j.scene.planes) % 16 == 0) &&
+                        (((size_t)j.scene.stride * es) % 16 == 0) &&
+                        (reinterpret_cast<uintptr_t>(j.d_keep) % 4 == 0);
+        b.pair_store = (reinterpret_cast<uintptr_t>(j.out.planes) % 4 == 0) && (j.out.stride % 2 == 0);
+    }
+    if (tiles > INT32_MAX || blocks > INT32_MAX) return REFINE_E_UNSUPPORTED;
+    hipStream_t strm = static_cast<hipStream_t>(stream);
+    if (hipMemcpyAsync(d_table, table.data(), sizeof(BatchJob) * table.size(), hipMemcpyHostToDevice, strm) !=
+        hipSuccess)
+        return REFINE_E_HIP;
+    if (launch_stats_batch(d_table, n_jobs, (int)tiles, *params, strm) != hipSuccess) return REFINE_E_HIP;
+    if (launch_score_batch(d_table, n_jobs, (int)blocks, *params, strm) != hipSuccess) return REFINE_E_HIP;
+    if (launch_select_batch(d_table, n_jobs, (int)tiles, strm) != hipSuccess) return REFINE_E_HIP;
+    if (launch_compact_batch(d_table, n_jobs, (int)tiles, strm) != hipSuccess) return REFINE_E_HIP;
+    return REFINE_OK;
 }
 
 }  // extern "C"

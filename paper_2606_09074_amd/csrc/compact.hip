@@ -16,10 +16,10 @@ namespace refine {
 
 namespace {
 
-__global__ __launch_bounds__(kBlock) void compact_count(const uint8_t* __restrict__ keep, int n,
-                                                          uint32_t* __restrict__ tile_cnt)
+__device__ __forceinline__ void compact_count_body(const uint8_t* __restrict__ keep, int n,
+                                                          uint32_t* __restrict__ tile_cnt, int blk)
 {
-    const int base = blockIdx.x * kTile;
+    const int base = blk * kTile;
     uint32_t c = 0;
 #pragma unroll 4
     for (int k = 0; k < kItems; ++k) {
@@ -33,8 +33,14 @@ __global__ __launch_bounds__(kBlock) void compact_count(const uint8_t* __restric
     if (threadIdx.x == 0) {
         uint32_t t = 0;
         for (int w = 0; w < kWaves; ++w) t += red[w];
-        tile_cnt[blockIdx.x] = t;
+        tile_cnt[blk] = t;
     }
+}
+
+__global__ __launch_bounds__(kBlock) void compact_count(const uint8_t* __restrict__ keep, int n,
+                                                          uint32_t* __restrict__ tile_cnt)
+{
+    compact_count_body(keep, n, tile_cnt, blockIdx.x);
 }
 
 __global__ __launch_bounds__(kScanThreads) void compact_scan(const uint32_t* __restrict__ tile_cnt,
@@ -52,28 +58,28 @@ __global__ void compact_empty(int64_t* __restrict__ d_n_out)
 // many tiles, else the sum of the preceding tiles' counts; block 0 also
 // reports the total number of survivors.
 __device__ inline int64_t tile_start(const uint32_t* __restrict__ tile_cnt, const uint32_t* __restrict__ tile_off,
-                                     int ntiles, int off_from_scan, int64_t* __restrict__ d_n_out)
+                                     int ntiles, int off_from_scan, int64_t* __restrict__ d_n_out, int tile)
 {
-    if (blockIdx.x == 0 && d_n_out) {
+    if (tile == 0 && d_n_out) {
         const uint64_t total = block_sum_prefix(tile_cnt, ntiles);
         if (threadIdx.x == 0) *d_n_out = (int64_t)total;
     }
-    return off_from_scan ? (int64_t)tile_off[blockIdx.x] : (int64_t)block_sum_prefix(tile_cnt, blockIdx.x);
+    return off_from_scan ? (int64_t)tile_off[tile] : (int64_t)block_sum_prefix(tile_cnt, tile);
 }
 
 template <class E>
-__global__ __launch_bounds__(kBlock) void compact_scatter(const E* __restrict__ in, int64_t in_stride, int n,
+__device__ __forceinline__ void compact_scatter_body(const E* __restrict__ in, int64_t in_stride, int n,
                                                             const uint8_t* __restrict__ keep,
                                                             const uint32_t* __restrict__ tile_cnt,
                                                             const uint32_t* __restrict__ tile_off, int ntiles,
                                                             int off_from_scan, int64_t* __restrict__ d_n_out,
                                                             E* __restrict__ out, int64_t out_stride,
-                                                            int64_t capacity, int32_t* __restrict__ index_map)
+                                                            int64_t capacity, int32_t* __restrict__ index_map, int blk)
 {
-    const int64_t tstart = tile_start(tile_cnt, tile_off, ntiles, off_from_scan, d_n_out);
+    const int64_t tstart = tile_start(tile_cnt, tile_off, ntiles, off_from_scan, d_n_out, blk);
     __shared__ uint32_t cnt[kItems][kWaves];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int base = blockIdx.x * kTile;
+    const int base = blk * kTile;
     uint64_t kb[kItems];
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
@@ -117,6 +123,19 @@ __global__ __launch_bounds__(kBlock) void compact_scatter(const E* __restrict__ 
     }
 }
 
+template <class E>
+__global__ __launch_bounds__(kBlock) void compact_scatter(const E* __restrict__ in, int64_t in_stride, int n,
+                                                            const uint8_t* __restrict__ keep,
+                                                            const uint32_t* __restrict__ tile_cnt,
+                                                            const uint32_t* __restrict__ tile_off, int ntiles,
+                                                            int off_from_scan, int64_t* __restrict__ d_n_out,
+                                                            E* __restrict__ out, int64_t out_stride,
+                                                            int64_t capacity, int32_t* __restrict__ index_map)
+{
+    compact_scatter_body<E>(in, in_stride, n, keep, tile_cnt, tile_off, ntiles, off_from_scan, d_n_out, out,
+                            out_stride, capacity, index_map, blockIdx.x);
+}
+
 // compact_scatter for 16-byte aligned planes (stride a multiple of 16 bytes)
 // and a 4-byte aligned mask.  A tile is rows of 16 bytes per lane: 4 rows of
 // 1024 FP32 primitives, or 2 rows of 2048 2-byte primitives; each lane loads
@@ -143,23 +162,23 @@ __device__ inline void unpack16(const uint4& x, E (&v)[PER])
 }
 
 template <class E>
-__global__ __launch_bounds__(kBlock) void compact_scatter_lds(const E* __restrict__ in, int64_t in_stride, int n,
+__device__ __forceinline__ void compact_scatter_lds_body(const E* __restrict__ in, int64_t in_stride, int n,
                                                                 const uint8_t* __restrict__ keep,
                                                                 const uint32_t* __restrict__ tile_cnt,
                                                                 const uint32_t* __restrict__ tile_off, int ntiles,
                                                                 int off_from_scan, int64_t* __restrict__ d_n_out,
                                                                 E* __restrict__ out, int64_t out_stride,
                                                                 int64_t capacity, int32_t* __restrict__ index_map,
-                                                                int pair_store)
+                                                                int pair_store, int blk)
 {
     constexpr int PER = 16 / sizeof(E);               // primitives per lane per row
     constexpr int ROWS = kTile / (PER * kBlock);      // 4 or 2
     constexpr int kStagePlanes = 8 / sizeof(E);       // 32 KB of LDS
-    const int64_t out0 = tile_start(tile_cnt, tile_off, ntiles, off_from_scan, d_n_out);
+    const int64_t out0 = tile_start(tile_cnt, tile_off, ntiles, off_from_scan, d_n_out, blk);
     __shared__ uint32_t wtot[ROWS][kWaves];
     __shared__ E stage[kStagePlanes][kTile];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int base = blockIdx.x * kTile;
+    const int base = blk * kTile;
     uint32_t flags[ROWS], incl[ROWS];
 #pragma unroll
     for (int r = 0; r < ROWS; ++r) {
@@ -202,7 +221,7 @@ __global__ __launch_bounds__(kBlock) void compact_scatter_lds(const E* __restric
         row += tot;
     }
     const int64_t room = capacity - out0;
-    const int kept = (int)min((int64_t)tile_cnt[blockIdx.x], room > 0 ? room : (int64_t)0);
+    const int kept = (int)min((int64_t)tile_cnt[blk], room > 0 ? room : (int64_t)0);
     if (index_map) {
 #pragma unroll
         for (int r = 0; r < ROWS; ++r) {
@@ -262,6 +281,20 @@ __global__ __launch_bounds__(kBlock) void compact_scatter_lds(const E* __restric
 }
 
 template <class E>
+__global__ __launch_bounds__(kBlock) void compact_scatter_lds(const E* __restrict__ in, int64_t in_stride, int n,
+                                                                const uint8_t* __restrict__ keep,
+                                                                const uint32_t* __restrict__ tile_cnt,
+                                                                const uint32_t* __restrict__ tile_off, int ntiles,
+                                                                int off_from_scan, int64_t* __restrict__ d_n_out,
+                                                                E* __restrict__ out, int64_t out_stride,
+                                                                int64_t capacity, int32_t* __restrict__ index_map,
+                                                                int pair_store)
+{
+    compact_scatter_lds_body<E>(in, in_stride, n, keep, tile_cnt, tile_off, ntiles, off_from_scan, d_n_out, out,
+                                out_stride, capacity, index_map, pair_store, blockIdx.x);
+}
+
+template <class E>
 void launch_compact_t(const E* in, int64_t in_stride, int n, const uint8_t* d_keep, E* out, int64_t out_stride,
                       int64_t capacity, int32_t* d_index_map, int64_t* d_n_out, const Workspace& ws, int ntiles,
                       int from_scan, hipStream_t stream)
@@ -279,7 +312,48 @@ void launch_compact_t(const E* in, int64_t in_stride, int n, const uint8_t* d_ke
                            d_index_map);
 }
 
+// Grouped launches over the jobs of a batch.  The tile offsets come from the
+// per-block sums of the job's preceding tiles (jobs of a batch have at most
+// kPrefixTilesMax tiles).
+__global__ __launch_bounds__(kBlock) void compact_count_batch(const BatchJob* __restrict__ jobs, int nj)
+{
+    const BatchJob& b = jobs[batch_job_of<true>(jobs, nj, blockIdx.x)];
+    compact_count_body(b.keep, b.n, b.tile_cnt, (int)blockIdx.x - b.tile0);
+}
+
+template <class E>
+__device__ __forceinline__ void compact_job_tile(const BatchJob& b, int tile)
+{
+    const int ntiles = (int)num_tiles(b.n);
+    if (b.vec_compact)
+        compact_scatter_lds_body<E>(static_cast<const E*>(b.planes), b.stride, b.n, b.keep, b.tile_cnt, nullptr,
+                                    ntiles, 0, b.n_out, static_cast<E*>(b.out), b.out_stride, b.capacity,
+                                    b.index_map, b.pair_store, tile);
+    else
+        compact_scatter_body<E>(static_cast<const E*>(b.planes), b.stride, b.n, b.keep, b.tile_cnt, nullptr,
+                                ntiles, 0, b.n_out, static_cast<E*>(b.out), b.out_stride, b.capacity, b.index_map,
+                                tile);
+}
+
+__global__ __launch_bounds__(kBlock) void compact_scatter_batch(const BatchJob* __restrict__ jobs, int nj)
+{
+    const BatchJob& b = jobs[batch_job_of<true>(jobs, nj, blockIdx.x)];
+    const int tile = (int)blockIdx.x - b.tile0;
+    if (storage_bytes(b.st) == 4)
+        compact_job_tile<uint32_t>(b, tile);
+    else
+        compact_job_tile<uint16_t>(b, tile);
+}
+
 }  // namespace
+
+hipError_t launch_compact_batch(const BatchJob* d_jobs, int n_jobs, int total_tiles, hipStream_t stream)
+{
+    hipLaunchKernelGGL(compact_count_batch, dim3(total_tiles), dim3(kBlock), 0, stream, d_jobs, n_jobs);
+    hipLaunchKernelGGL(compact_scatter_batch, dim3(total_tiles), dim3(kBlock), 0, stream, d_jobs, n_jobs);
+    return hipGetLastError();
+}
+
 
 hipError_t launch_compact(const void* in, int st, int64_t in_stride, int64_t n, const uint8_t* d_keep, void* out,
                           int64_t out_stride, int64_t capacity, int32_t* d_index_map, int64_t* d_n_out,

@@ -20,7 +20,7 @@ enum Storage : int {
     kStoreBF16F16 = 1    // BF16, FP16
 };
 
-inline size_t storage_bytes(int st) { return st == kStoreF32 ? 4 : 2; }
+__host__ __device__ inline size_t storage_bytes(int st) { return st == kStoreF32 ? 4 : 2; }
 constexpr int kCamFields = 18;
 constexpr int kBlock = 256;        // threads per block of the tile kernels (4 wave64)
 constexpr int kWaves = kBlock / 64;
@@ -107,7 +107,58 @@ struct Workspace {
     unsigned long long* evaluated;   // [kEvalSlots] pairs evaluated by the last view loop
 };
 
-inline int64_t num_tiles(int64_t n) { return (n + kTile - 1) / kTile; }
+__host__ __device__ inline int64_t num_tiles(int64_t n) { return (n + kTile - 1) / kTile; }
+
+// Views scored: all, or the subsample of n_sub_views (views floor(j V / m)).
+inline int views_of(const refine_params& prm, int32_t n_views)
+{
+    return (prm.n_sub_views > 0 && prm.n_sub_views < n_views) ? prm.n_sub_views : n_views;
+}
+
+// One prune of a grouped launch (refine_prune_batch): its inputs, outputs,
+// workspace slices and its first tile / 256-primitive block in the batch's
+// numbering.  A device copy of the table is read by every grouped kernel.
+struct BatchJob {
+    const void* planes;
+    int64_t stride;
+    int32_t n;
+    int32_t st;              // Storage
+    const float* cams;
+    int32_t n_views;
+    int32_t nv;              // views actually scored (subsampling)
+    refine_stats_t* stats;
+    float* scores;
+    uint8_t* keep;
+    int64_t n_prune;
+    int64_t* n_keep_out;
+    void* out;
+    int64_t out_stride;
+    int64_t capacity;
+    int32_t* index_map;
+    int64_t* n_out;
+    double* stat_part;       // [ntiles][kStatSlots]
+    struct CamRec* cam_rec;  // [nv]
+    struct SelectState* sel;
+    uint32_t* hist;          // [kSelectHistWords]
+    uint32_t* tile_cnt;      // [ntiles]
+    int32_t tile0;           // first tile in the batch's tile numbering
+    int32_t block0;          // first 256-primitive block in the batch's block numbering
+    int32_t vec_compact;     // 16-byte-load compaction applies
+    int32_t pair_store;      // 2-byte output written two elements per store
+};
+
+// Index of the job whose range [first, next first) holds b (first of job 0 is 0).
+template <bool BY_TILE>
+__device__ inline int batch_job_of(const BatchJob* __restrict__ jobs, int nj, int b)
+{
+    int lo = 0, hi = nj - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        const int first = BY_TILE ? jobs[mid].tile0 : jobs[mid].block0;
+        if (first <= b) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
 
 // Bytes of a workspace for (n, n_views); fills *ws when base != nullptr.  With
 // score == false only the prefix used by stats/select/compact is counted.
@@ -120,6 +171,12 @@ hipError_t launch_stats(const void* planes, int st, int64_t stride, int64_t n, c
 hipError_t launch_score_prepare(const void* planes, int st, int64_t stride, int64_t n, const float* d_cams,
                                 int32_t n_views, const refine_params& prm, const refine_stats_t* d_stats,
                                 const Workspace& ws, hipStream_t stream);
+hipError_t launch_stats_batch(const BatchJob* d_jobs, int n_jobs, int total_tiles, const refine_params& prm,
+                              hipStream_t stream);
+hipError_t launch_score_batch(const BatchJob* d_jobs, int n_jobs, int total_blocks, const refine_params& prm,
+                              hipStream_t stream);
+hipError_t launch_select_batch(const BatchJob* d_jobs, int n_jobs, int total_tiles, hipStream_t stream);
+hipError_t launch_compact_batch(const BatchJob* d_jobs, int n_jobs, int total_tiles, hipStream_t stream);
 hipError_t launch_score_cameras(const float* d_cams, int32_t n_views, const refine_params& prm, const Workspace& ws,
                                 hipStream_t stream);
 hipError_t launch_score_views(const void* planes, int st, int64_t stride, int64_t n, int32_t n_views,

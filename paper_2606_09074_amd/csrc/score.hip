@@ -59,14 +59,10 @@ constexpr float kCullMargin = 1.01f;
 constexpr int64_t kBinnedMinPrims = 65536;
 constexpr int kDefaultPPL = 1;   // binned records per lane unless the caller picks
 
-// Also clears the binning cell counts (cell_cnt is null on the direct path).
-__global__ __launch_bounds__(kBlock) void camera_prep(const float* __restrict__ cams, int n_views, int nv,
-                                                        float clamp_k, CamRec* __restrict__ out,
-                                                        CullRec* __restrict__ cull, uint32_t* __restrict__ cell_cnt)
+// The records of view slot j (cull may be null: no culling records).
+__device__ __forceinline__ void camera_prep_body(const float* __restrict__ cams, int n_views, int nv, float clamp_k,
+                                                 CamRec* __restrict__ out, CullRec* __restrict__ cull, int j)
 {
-    const int j = blockIdx.x * kBlock + threadIdx.x;
-    if (cell_cnt && j < kCells) cell_cnt[j] = 0u;
-    if (j >= nv) return;
     const int v = (nv == n_views) ? j : (int)(((int64_t)j * n_views) / nv);
     const float* c = cams + (int64_t)v * kCamFields;
     const float fx = c[12], fy = c[13], cx = c[14], cy = c[15], W = c[16], H = c[17];
@@ -93,6 +89,7 @@ __global__ __launch_bounds__(kBlock) void camera_prep(const float* __restrict__ 
 #pragma unroll
     for (int k = 0; k < 14; ++k) r.pad[k] = 0.0f;
     out[j] = r;
+    if (!cull) return;
 
     // culling half-spaces: u + r > 0, W - u + r > 0, v + r > 0, H - v + r > 0,
     // multiplied by z > 0 and written as n . mu + d + r z > 0 with r z <= 3 s_max kv
@@ -122,6 +119,16 @@ __global__ __launch_bounds__(kBlock) void camera_prep(const float* __restrict__ 
 #pragma unroll
     for (int k = 0; k < 7; ++k) q.pad[k] = 0.0f;
     cull[j] = q;
+}
+
+// Also clears the binning cell counts (cell_cnt is null on the direct path).
+__global__ __launch_bounds__(kBlock) void camera_prep(const float* __restrict__ cams, int n_views, int nv,
+                                                        float clamp_k, CamRec* __restrict__ out,
+                                                        CullRec* __restrict__ cull, uint32_t* __restrict__ cell_cnt)
+{
+    const int j = blockIdx.x * kBlock + threadIdx.x;
+    if (cell_cnt && j < kCells) cell_cnt[j] = 0u;
+    if (j < nv) camera_prep_body(cams, n_views, nv, clamp_k, out, cull, j);
 }
 
 // Registers a lane keeps for one primitive across the view loop.
@@ -230,18 +237,50 @@ __device__ __forceinline__ void eval_pair(const Cam& c, Prim& p, float eta, floa
 }
 
 template <int PROJ, int ST>
-__global__ __launch_bounds__(kBlock) void score_direct(const void* __restrict__ planes, int64_t stride, int n,
-                                                         const CamRec* __restrict__ cams, int nv,
-                                                         const refine_stats_t* __restrict__ st, float eta,
-                                                         float z_near, int vis_alpha, float* __restrict__ out)
+__device__ __forceinline__ void score_direct_body(const void* __restrict__ planes, int64_t stride, int n,
+                                                  const CamRec* __restrict__ cams, int nv,
+                                                  const refine_stats_t* __restrict__ st, float eta, float z_near,
+                                                  int vis_alpha, float* __restrict__ out, int i)
 {
-    const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     Prim p;
     float pre, smax;
     activate<ST>(planes, stride, i, p, pre, smax, st, PROJ, vis_alpha);
     for (int v = 0; v < nv; ++v) eval_pair<PROJ>(cams[v], p, eta, z_near);
     out[i] = pre * p.S / (float)nv;
+}
+
+template <int PROJ, int ST>
+__global__ __launch_bounds__(kBlock) void score_direct(const void* __restrict__ planes, int64_t stride, int n,
+                                                         const CamRec* __restrict__ cams, int nv,
+                                                         const refine_stats_t* __restrict__ st, float eta,
+                                                         float z_near, int vis_alpha, float* __restrict__ out)
+{
+    score_direct_body<PROJ, ST>(planes, stride, n, cams, nv, st, eta, z_near, vis_alpha, out,
+                                blockIdx.x * kBlock + threadIdx.x);
+}
+
+// Grouped launches: the camera records of one job per block, and the direct
+// view loop over 256 primitives of one job per block.
+__global__ __launch_bounds__(kBlock) void camera_prep_batch(const BatchJob* __restrict__ jobs, float clamp_k)
+{
+    const BatchJob& b = jobs[blockIdx.x];
+    for (int j = threadIdx.x; j < b.nv; j += kBlock)
+        camera_prep_body(b.cams, b.n_views, b.nv, clamp_k, b.cam_rec, nullptr, j);
+}
+
+template <int PROJ>
+__global__ __launch_bounds__(kBlock) void score_direct_batch(const BatchJob* __restrict__ jobs, int nj, float eta,
+                                                               float z_near, int vis_alpha)
+{
+    const BatchJob& b = jobs[batch_job_of<false>(jobs, nj, blockIdx.x)];
+    const int i = ((int)blockIdx.x - b.block0) * kBlock + (int)threadIdx.x;
+    if (b.st == kStoreF32)
+        score_direct_body<PROJ, kStoreF32>(b.planes, b.stride, b.n, b.cam_rec, b.nv, b.stats, eta, z_near,
+                                           vis_alpha, b.scores, i);
+    else
+        score_direct_body<PROJ, kStoreBF16F16>(b.planes, b.stride, b.n, b.cam_rec, b.nv, b.stats, eta, z_near,
+                                               vis_alpha, b.scores, i);
 }
 
 // ------------------------------------------------------------- binned path
@@ -568,10 +607,6 @@ void views_mode(const void* planes, int64_t stride, int n, const refine_params& 
     }
 }
 
-int views_of(const refine_params& prm, int32_t n_views)
-{
-    return (prm.n_sub_views > 0 && prm.n_sub_views < n_views) ? prm.n_sub_views : n_views;
-}
 
 bool binned_path(const refine_params& prm, int64_t n)
 {
@@ -610,6 +645,29 @@ hipError_t launch_score_prepare(const void* planes, int st, int64_t stride, int6
     dispatch_mode(prm.proj_mode, st, [&](auto proj_c, auto st_c) {
         prepare_mode<decltype(proj_c)::value, decltype(st_c)::value>(planes, stride, (int)n, prm, d_stats, ws, stream);
     });
+    return hipGetLastError();
+}
+
+hipError_t launch_score_batch(const BatchJob* d_jobs, int n_jobs, int total_blocks, const refine_params& prm,
+                              hipStream_t stream)
+{
+    const int vis = prm.vis_mode == REFINE_VIS_ALPHA ? 1 : 0;
+    const float eta = (float)prm.eta, zn = (float)prm.z_near;
+    hipLaunchKernelGGL(camera_prep_batch, dim3(n_jobs), dim3(kBlock), 0, stream, d_jobs, (float)prm.clamp_k);
+    switch (prm.proj_mode) {
+    case REFINE_PROJ_COV:
+        hipLaunchKernelGGL((score_direct_batch<REFINE_PROJ_COV>), dim3(total_blocks), dim3(kBlock), 0, stream, d_jobs,
+                           n_jobs, eta, zn, vis);
+        break;
+    case REFINE_PROJ_DEPTH:
+        hipLaunchKernelGGL((score_direct_batch<REFINE_PROJ_DEPTH>), dim3(total_blocks), dim3(kBlock), 0, stream,
+                           d_jobs, n_jobs, eta, zn, vis);
+        break;
+    default:
+        hipLaunchKernelGGL((score_direct_batch<REFINE_PROJ_NONE>), dim3(total_blocks), dim3(kBlock), 0, stream,
+                           d_jobs, n_jobs, eta, zn, vis);
+        break;
+    }
     return hipGetLastError();
 }
 

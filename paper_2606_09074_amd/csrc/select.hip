@@ -48,7 +48,7 @@ __global__ void select_init(SelectState* __restrict__ st, uint32_t* __restrict__
 
 // Locate the bucket holding the target rank in this pass's histogram (the
 // sum of its copies) and fold it into the prefix (one block).
-__global__ __launch_bounds__(kScanThreads) void select_find(SelectState* __restrict__ st,
+__device__ __forceinline__ void select_find_body(SelectState* __restrict__ st,
                                                               const uint32_t* __restrict__ hist, int shift, int bits,
                                                               int last_pass)
 {
@@ -106,13 +106,20 @@ __global__ __launch_bounds__(kScanThreads) void select_find(SelectState* __restr
     }
 }
 
+__global__ __launch_bounds__(kScanThreads) void select_find(SelectState* __restrict__ st,
+                                                              const uint32_t* __restrict__ hist, int shift, int bits,
+                                                              int last_pass)
+{
+    select_find_body(st, hist, shift, bits, last_pass);
+}
+
 // One tile per block: all 16 keys of a thread are loaded before any is
 // counted, and the crowded bins (many equal exponents, exact zeros) are
 // counted per wave -- the lanes that share the lowest counting lane's bin
 // add with one LDS atomic.
-__global__ __launch_bounds__(kBlock) void select_hist(const float* __restrict__ scores, int n,
+__device__ __forceinline__ void select_hist_body(const float* __restrict__ scores, int n,
                                                         const SelectState* __restrict__ st, int shift, int bits,
-                                                        uint32_t* __restrict__ hist)
+                                                        uint32_t* __restrict__ hist, int blk)
 {
     constexpr uint32_t kNoBin = 0xFFFFFFFFu;
     __shared__ uint32_t h[kHistBins];
@@ -120,7 +127,7 @@ __global__ __launch_bounds__(kBlock) void select_hist(const float* __restrict__ 
     for (int b = threadIdx.x; b < nb; b += kBlock) h[b] = 0u;
     const uint32_t prefix = st->prefix, mask = st->mask;
     const uint32_t dmask = (uint32_t)nb - 1u;
-    const int base = blockIdx.x * kTile;
+    const int base = blk * kTile;
     float v[kItems];
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
@@ -148,16 +155,23 @@ __global__ __launch_bounds__(kBlock) void select_hist(const float* __restrict__ 
     __syncthreads();
     for (int b = threadIdx.x; b < nb; b += kBlock) {
         const uint32_t c = h[b];
-        if (c) atomicAdd(&hist[(blockIdx.x % kHistCopies) * kHistBins + b], c);
+        if (c) atomicAdd(&hist[(blk % kHistCopies) * kHistBins + b], c);
     }
 }
 
-__global__ __launch_bounds__(kBlock) void select_count(const float* __restrict__ scores, int n,
+__global__ __launch_bounds__(kBlock) void select_hist(const float* __restrict__ scores, int n,
+                                                        const SelectState* __restrict__ st, int shift, int bits,
+                                                        uint32_t* __restrict__ hist)
+{
+    select_hist_body(scores, n, st, shift, bits, hist, blockIdx.x);
+}
+
+__device__ __forceinline__ void select_count_body(const float* __restrict__ scores, int n,
                                                          const SelectState* __restrict__ st,
-                                                         uint32_t* __restrict__ tile_cnt)
+                                                         uint32_t* __restrict__ tile_cnt, int blk)
 {
     const uint32_t T = st->threshold;
-    const int base = blockIdx.x * kTile;
+    const int base = blk * kTile;
     uint32_t c = 0;
 #pragma unroll 4
     for (int k = 0; k < kItems; ++k) {
@@ -171,8 +185,15 @@ __global__ __launch_bounds__(kBlock) void select_count(const float* __restrict__
     if (threadIdx.x == 0) {
         uint32_t t = 0;
         for (int w = 0; w < kWaves; ++w) t += red[w];
-        tile_cnt[blockIdx.x] = t;
+        tile_cnt[blk] = t;
     }
+}
+
+__global__ __launch_bounds__(kBlock) void select_count(const float* __restrict__ scores, int n,
+                                                         const SelectState* __restrict__ st,
+                                                         uint32_t* __restrict__ tile_cnt)
+{
+    select_count_body(scores, n, st, tile_cnt, blockIdx.x);
 }
 
 __global__ __launch_bounds__(kScanThreads) void select_scan(const uint32_t* __restrict__ tile_cnt,
@@ -183,24 +204,24 @@ __global__ __launch_bounds__(kScanThreads) void select_scan(const uint32_t* __re
 
 // off_from_scan: the tile offsets come from select_scan (many tiles) instead
 // of a per-block sum of the preceding tiles' counts.
-__global__ __launch_bounds__(kBlock) void select_mask(const float* __restrict__ scores, int n,
+__device__ __forceinline__ void select_mask_body(const float* __restrict__ scores, int n,
                                                         const SelectState* __restrict__ st,
                                                         const uint32_t* __restrict__ tile_cnt,
                                                         const uint32_t* __restrict__ tile_off, int off_from_scan,
                                                         uint8_t* __restrict__ keep, int64_t* __restrict__ d_n_keep,
-                                                        uint32_t* __restrict__ d_threshold)
+                                                        uint32_t* __restrict__ d_threshold, int blk)
 {
     __shared__ uint32_t cnt[kItems][kWaves];
     const uint32_t T = st->threshold;
     const int64_t k_eq = st->k_eq;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (blk == 0 && threadIdx.x == 0) {
         if (d_n_keep) *d_n_keep = st->n_keep;
         if (d_threshold) *d_threshold = T;
     }
-    const int64_t tile_start = off_from_scan ? (int64_t)tile_off[blockIdx.x]
-                                             : (int64_t)block_sum_prefix(tile_cnt, blockIdx.x);
+    const int64_t tile_start = off_from_scan ? (int64_t)tile_off[blk]
+                                             : (int64_t)block_sum_prefix(tile_cnt, blk);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int base = blockIdx.x * kTile;
+    const int base = blk * kTile;
     uint32_t key[kItems];
     uint64_t eqb[kItems];
 #pragma unroll
@@ -228,6 +249,16 @@ __global__ __launch_bounds__(kBlock) void select_mask(const float* __restrict__ 
     }
 }
 
+__global__ __launch_bounds__(kBlock) void select_mask(const float* __restrict__ scores, int n,
+                                                        const SelectState* __restrict__ st,
+                                                        const uint32_t* __restrict__ tile_cnt,
+                                                        const uint32_t* __restrict__ tile_off, int off_from_scan,
+                                                        uint8_t* __restrict__ keep, int64_t* __restrict__ d_n_keep,
+                                                        uint32_t* __restrict__ d_threshold)
+{
+    select_mask_body(scores, n, st, tile_cnt, tile_off, off_from_scan, keep, d_n_keep, d_threshold, blockIdx.x);
+}
+
 __global__ void select_outputs(const SelectState* __restrict__ st, int64_t* __restrict__ d_n_keep,
                                uint32_t* __restrict__ d_threshold)
 {
@@ -235,7 +266,65 @@ __global__ void select_outputs(const SelectState* __restrict__ st, int64_t* __re
     if (d_threshold) *d_threshold = st->threshold;
 }
 
+// Grouped launches over the jobs of a batch (jobs that prune nothing skip the
+// histogram passes, as the single-job launch sequence does).
+__global__ __launch_bounds__(kBlock) void select_init_batch(const BatchJob* __restrict__ jobs)
+{
+    const BatchJob& b = jobs[blockIdx.x];
+    for (int w = threadIdx.x; w < kSelectHistWords; w += kBlock) b.hist[w] = 0u;
+    if (threadIdx.x == 0) {
+        SelectState s = {};
+        s.n = b.n;
+        s.n_prune = b.n_prune;
+        s.rank = b.n_prune - 1;
+        s.n_keep = b.n - b.n_prune;
+        *b.sel = s;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void select_hist_batch(const BatchJob* __restrict__ jobs, int nj, int pass)
+{
+    const BatchJob& b = jobs[batch_job_of<true>(jobs, nj, blockIdx.x)];
+    if (b.n_prune == 0) return;
+    select_hist_body(b.scores, b.n, b.sel, kPassShift[pass], kPassBits[pass],
+                     b.hist + pass * kHistCopies * kHistBins, (int)blockIdx.x - b.tile0);
+}
+
+__global__ __launch_bounds__(kScanThreads) void select_find_batch(const BatchJob* __restrict__ jobs, int pass)
+{
+    const BatchJob& b = jobs[blockIdx.x];
+    if (b.n_prune == 0) return;
+    select_find_body(b.sel, b.hist + pass * kHistCopies * kHistBins, kPassShift[pass], kPassBits[pass],
+                     pass == 2 ? 1 : 0);
+}
+
+__global__ __launch_bounds__(kBlock) void select_count_batch(const BatchJob* __restrict__ jobs, int nj)
+{
+    const BatchJob& b = jobs[batch_job_of<true>(jobs, nj, blockIdx.x)];
+    select_count_body(b.scores, b.n, b.sel, b.tile_cnt, (int)blockIdx.x - b.tile0);
+}
+
+__global__ __launch_bounds__(kBlock) void select_mask_batch(const BatchJob* __restrict__ jobs, int nj)
+{
+    const BatchJob& b = jobs[batch_job_of<true>(jobs, nj, blockIdx.x)];
+    select_mask_body(b.scores, b.n, b.sel, b.tile_cnt, nullptr, 0, b.keep, b.n_keep_out, nullptr,
+                     (int)blockIdx.x - b.tile0);
+}
+
 }  // namespace
+
+hipError_t launch_select_batch(const BatchJob* d_jobs, int n_jobs, int total_tiles, hipStream_t stream)
+{
+    hipLaunchKernelGGL(select_init_batch, dim3(n_jobs), dim3(kBlock), 0, stream, d_jobs);
+    for (int p = 0; p < 3; ++p) {
+        hipLaunchKernelGGL(select_hist_batch, dim3(total_tiles), dim3(kBlock), 0, stream, d_jobs, n_jobs, p);
+        hipLaunchKernelGGL(select_find_batch, dim3(n_jobs), dim3(kScanThreads), 0, stream, d_jobs, p);
+    }
+    hipLaunchKernelGGL(select_count_batch, dim3(total_tiles), dim3(kBlock), 0, stream, d_jobs, n_jobs);
+    hipLaunchKernelGGL(select_mask_batch, dim3(total_tiles), dim3(kBlock), 0, stream, d_jobs, n_jobs);
+    return hipGetLastError();
+}
+
 
 hipError_t launch_select(const float* d_scores, int64_t n, int64_t n_prune, uint8_t* d_keep, int64_t* d_n_keep,
                          uint32_t* d_threshold, const Workspace& ws, hipStream_t stream)

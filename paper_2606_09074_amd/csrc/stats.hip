@@ -118,10 +118,9 @@ __device__ void reduce_and_store(Acc& a, int tile, double* __restrict__ part)
 
 
 template <int ST>
-__global__ __launch_bounds__(kBlock) void stats_partial(const void* __restrict__ planes, int64_t stride,
-                                                          int n, float eta, double* __restrict__ part)
+__device__ __forceinline__ void stats_partial_body(const void* __restrict__ planes, int64_t stride, int n,
+                                                   float eta, double* __restrict__ part, int tile)
 {
-    const int tile = blockIdx.x;
     const int base = tile * kTile;
     Acc a;
 #pragma unroll 4
@@ -136,8 +135,15 @@ __global__ __launch_bounds__(kBlock) void stats_partial(const void* __restrict__
     reduce_and_store(a, tile, part);
 }
 
-__global__ __launch_bounds__(kBlock) void stats_finalize(const double* __restrict__ part, int ntiles, int64_t n,
-                                                           refine_params prm, refine_stats_t* __restrict__ out)
+template <int ST>
+__global__ __launch_bounds__(kBlock) void stats_partial(const void* __restrict__ planes, int64_t stride,
+                                                          int n, float eta, double* __restrict__ part)
+{
+    stats_partial_body<ST>(planes, stride, n, eta, part, blockIdx.x);
+}
+
+__device__ __forceinline__ void stats_finalize_body(const double* __restrict__ part, int ntiles, int64_t n,
+                                                    const refine_params& prm, refine_stats_t* __restrict__ out)
 {
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     float bmin[3] = {INFINITY, INFINITY, INFINITY}, bmax[3] = {-INFINITY, -INFINITY, -INFINITY};
@@ -213,7 +219,39 @@ __global__ __launch_bounds__(kBlock) void stats_finalize(const double* __restric
     *out = r;
 }
 
+__global__ __launch_bounds__(kBlock) void stats_finalize(const double* __restrict__ part, int ntiles, int64_t n,
+                                                           refine_params prm, refine_stats_t* __restrict__ out)
+{
+    stats_finalize_body(part, ntiles, n, prm, out);
+}
+
+// Grouped launches: one tile of one job per block / one job per block.
+__global__ __launch_bounds__(kBlock) void stats_partial_batch(const BatchJob* __restrict__ jobs, int nj, float eta)
+{
+    const BatchJob& b = jobs[batch_job_of<true>(jobs, nj, blockIdx.x)];
+    const int tile = (int)blockIdx.x - b.tile0;
+    if (b.st == kStoreF32)
+        stats_partial_body<kStoreF32>(b.planes, b.stride, b.n, eta, b.stat_part, tile);
+    else
+        stats_partial_body<kStoreBF16F16>(b.planes, b.stride, b.n, eta, b.stat_part, tile);
+}
+
+__global__ __launch_bounds__(kBlock) void stats_finalize_batch(const BatchJob* __restrict__ jobs, refine_params prm)
+{
+    const BatchJob& b = jobs[blockIdx.x];
+    stats_finalize_body(b.stat_part, (int)num_tiles(b.n), b.n, prm, b.stats);
+}
+
 }  // namespace
+
+hipError_t launch_stats_batch(const BatchJob* d_jobs, int n_jobs, int total_tiles, const refine_params& prm,
+                              hipStream_t stream)
+{
+    hipLaunchKernelGGL(stats_partial_batch, dim3(total_tiles), dim3(kBlock), 0, stream, d_jobs, n_jobs,
+                       (float)prm.eta);
+    hipLaunchKernelGGL(stats_finalize_batch, dim3(n_jobs), dim3(kBlock), 0, stream, d_jobs, prm);
+    return hipGetLastError();
+}
 
 hipError_t launch_stats(const void* planes, int st, int64_t stride, int64_t n, const refine_params& prm,
                         refine_stats_t* d_stats, const Workspace& ws, hipStream_t stream)

@@ -204,3 +204,43 @@ def test_compact_validation(lib):
     assert call(src=_scene(n=100, **mixed), dst=_scene(n=50, planes=FAKE + 11798, **mixed)) == E
     assert call(dst=_scene(n=50, stride=10, planes=0x4000000)) == E
     assert call(wsb=8) == _lib.REFINE_E_WORKSPACE
+
+
+def test_batch_validation(lib):
+    from paper_2606_09074_amd import _lib
+    E, U, W = _lib.REFINE_E_INVALID, _lib.REFINE_E_UNSUPPORTED, _lib.REFINE_E_WORKSPACE
+    p = _lib.default_params()
+
+    def job(**kw):
+        j = _lib.PruneJob()
+        j.scene = _scene(n=kw.get("n", 100), dtype=kw.get("dtype", 0), sh_dtype=kw.get("sh_dtype", 0))
+        j.cams = kw.get("cams", FAKE)
+        j.n_views = kw.get("nv", 16)
+        j.reserved = kw.get("reserved", 0)
+        j.ratio = kw.get("ratio", 0.5)
+        j.stats, j.scores, j.keep = kw.get("stats", FAKE), kw.get("scores", FAKE), kw.get("keep", FAKE)
+        j.out = _scene(n=50, planes=0x4000000, dtype=kw.get("odtype", 0), sh_dtype=kw.get("osh", 0))
+        return j
+
+    def size(*jobs, prm=p):
+        arr = (_lib.PruneJob * len(jobs))(*jobs)
+        out = ctypes.c_size_t(0)
+        return lib.refine_prune_batch_workspace_size(arr, len(jobs), ctypes.byref(prm), ctypes.byref(out)), out.value
+
+    def run(*jobs, wsb=1 << 30, ws=FAKE):
+        arr = (_lib.PruneJob * len(jobs))(*jobs)
+        return lib.refine_prune_batch(arr, len(jobs), ctypes.byref(p), ws, wsb, None)
+    rc, b1 = size(job())
+    assert rc == 0 and b1 > 0
+    rc, b2 = size(job(), job(n=5000))
+    assert rc == 0 and b2 > b1
+    assert lib.refine_prune_batch_workspace_size(None, 1, ctypes.byref(p), ctypes.byref(ctypes.c_size_t())) == E
+    arr = (_lib.PruneJob * 1)(job())
+    assert lib.refine_prune_batch_workspace_size(arr, 0, ctypes.byref(p), ctypes.byref(ctypes.c_size_t())) == E
+    for bad in (dict(n=0), dict(ratio=1.0), dict(ratio=0.0), dict(cams=0), dict(nv=0), dict(stats=0),
+                dict(scores=0), dict(keep=0), dict(reserved=1), dict(odtype=1, osh=2)):
+        assert size(job(**bad))[0] == E, bad
+        assert run(job(**bad)) == E, bad
+    assert size(job(n=4096 * 4096 + 1))[0] == U
+    assert run(job(), wsb=b1 - 1) == W
+    assert run(job(), ws=0) == W

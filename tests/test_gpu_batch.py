@@ -1,0 +1,85 @@
+"""Batched pruning (one grouped launch per kernel for many scenes) gives,
+for every job, the same statistics, scores, mask and survivors, bit for
+bit, as the single-scene calls with the direct scoring path; and the scores
+match the oracle."""
+import numpy as np
+import pytest
+
+from paper_2606_09074_amd import synth
+from tests.gpu_common import check_scores, gpu_params, log, oracle_all, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2606_09074_amd import _lib
+    _lib.load()
+
+
+def _jobs():
+    """Ragged sizes, both storages, several rigs and ratios, one padded stride
+    (scalar compaction), one output below the survivor count."""
+    base = synth.make_planes(synth.SMALL)
+    spec = [  # (n, stride, storage, views, ratio, capacity fraction)
+        (1, 1, "f32", 16, 0.5, 1.0), (777, 777, "f32", 7, 0.3, 1.0), (4096, 4096, "mixed", 16, 0.9, 1.0),
+        (4097, 4103, "f32", 33, 0.5, 1.0), (20000, 20000, "mixed", 50, 0.66, 1.0),
+        (50000, 50000, "f32", 16, 0.5, 0.8), (9001, 9003, "mixed", 5, 0.41, 1.0)]
+    out = []
+    for n, stride, store, V, ratio, capf in spec:
+        pl = np.zeros((59, stride), np.float32)
+        pl[:, :n] = base[:, :n]
+        if store == "mixed":
+            pl = synth.quantize_bf16_f16(pl)
+        out.append((pl, n, synth.ring_cameras(V), ratio, capf))
+    return out
+
+
+def test_batch_matches_single_scene_calls():
+    import torch
+
+    from paper_2606_09074_amd import _lib, api
+    dev = torch.device("cuda:0")
+    jobs, singles = [], []
+    for pl_np, n, cams_np, ratio, capf in _jobs():
+        pl = torch.from_numpy(pl_np).to(dev)
+        cams = torch.from_numpy(cams_np).to(dev)
+        cap = int((n - api.prune_count(n, ratio)) * capf)
+        fill = float("nan") if pl.dtype == torch.float32 else -12345
+        jobs.append({"planes": pl, "n": n, "cams": cams, "ratio": ratio,
+                     "stats": torch.zeros(_lib.STATS_BYTES, dtype=torch.uint8, device=dev),
+                     "scores": torch.full((n,), float("nan"), dtype=torch.float32, device=dev),
+                     "keep": torch.full((n,), 7, dtype=torch.uint8, device=dev),
+                     "n_keep": torch.full((1,), -1, dtype=torch.int64, device=dev),
+                     "out": torch.full((59, cap + 3), fill, dtype=pl.dtype, device=dev), "capacity": cap,
+                     "index_map": torch.full((cap + 3,), -7, dtype=torch.int32, device=dev),
+                     "n_out": torch.full((1,), -1, dtype=torch.int64, device=dev)})
+        singles.append(run_gpu(pl_np, cams_np, n=n, ratio=ratio, params=gpu_params(score_path=1)))
+    prm = gpu_params()
+    ws = torch.empty(api.batch_workspace_size(jobs, prm), dtype=torch.uint8, device=dev)
+    log(f"batch of {len(jobs)} jobs, n = {[j['n'] for j in jobs]}, workspace {ws.numel()} B")
+    api.refine_prune_batch(jobs, ws, prm)
+    torch.cuda.synchronize()
+    for j, r, (pl_np, n, cams_np, ratio, capf) in zip(jobs, singles, _jobs()):
+        what = f"job n={n} V={cams_np.shape[0]} ratio={ratio} {pl_np.dtype}"
+        st = api.stats_from_tensor(j["stats"])
+        for k in ("ybar", "f_col", "f_opa", "f_gem", "lambda", "n", "n_nonfinite", "bbox_min", "bbox_max"):
+            assert st[k] == r["stats"][k], (what, k)
+        np.testing.assert_array_equal(j["scores"].cpu().numpy().view(np.uint32), r["scores"].view(np.uint32))
+        keep = j["keep"].cpu().numpy()
+        np.testing.assert_array_equal(keep, r["keep"])
+        k = int(keep.sum())
+        assert int(j["n_keep"].item()) == k and int(j["n_out"].item()) == k
+        cap = j["capacity"]
+        sel = np.nonzero(keep)[0][:cap]
+        out = j["out"].cpu().numpy()
+        bits = np.uint32 if pl_np.dtype == np.float32 else np.uint16
+        np.testing.assert_array_equal(out[:, :cap].view(bits), pl_np[:, sel].view(bits))
+        np.testing.assert_array_equal(j["index_map"].cpu().numpy()[:cap], sel.astype(np.int32))
+        tail = out[:, cap:]
+        assert np.all(np.isnan(tail)) if pl_np.dtype == np.float32 else np.all(tail == -12345)
+        deq = pl_np if pl_np.dtype == np.float32 else synth.dequantize_bf16_f16(pl_np)
+        F, lam, D, lo, hi = oracle_all(deq, cams_np, n=n)
+        check_scores(j["scores"].cpu().numpy(), D, lo, hi, what)
