@@ -275,8 +275,9 @@ def serve_bench(args) -> dict:
     tuner.tune(f32[-1], lambda V: torch.from_numpy(synth.ring_cameras(V)).to(dev), buckets, reps=3)
     log(f"serve: tuned {len(buckets)} buckets: {sorted(tuner.table.items())}")
 
-    def run(scenes, arr, slots, prepare=True):
-        srv = serve.Server(dev, slots=slots, tuner=tuner, prepare_scenes=prepare)
+    def run(scenes, arr, slots, prepare=True, pack=True):
+        srv = serve.Server(dev, slots=slots, tuner=tuner, prepare_scenes=prepare,
+                           pack_max_n=(1 << 20) if pack else 0)
         for t in scenes:
             srv.add_scene(t)
         # warm the allocator and the kernels on every scene
@@ -297,7 +298,7 @@ def serve_bench(args) -> dict:
         dev_ms = [j.device_ms for j in fin]
         first = min(j.id for j in fin)
         order = [keeps[first + i] for i in range(len(fin))]
-        evals = sum(specs[sc].n * V for sc, V, _ in reqs)
+        evals = sum(scenes[sc].shape[1] * V for sc, V, _ in reqs)
         return {"p50_ms": round(serve.percentile(lat, 0.5), 3), "p99_ms": round(serve.percentile(lat, 0.99), 3),
                 "mean_ms": round(float(np.mean(lat)), 3), "max_ms": round(float(np.max(lat)), 3),
                 "device_p50_ms": round(serve.percentile(dev_ms, 0.5), 3),
@@ -317,14 +318,25 @@ def serve_bench(args) -> dict:
     burst = np.zeros(len(reqs))
     log("serve: burst (all jobs at once), with and without overlap")
     b4, _ = run(f32, burst, args.serve_slots)
-    b1, _ = run(f32, burst, 1)
+    b4n, _ = run(f32, burst, args.serve_slots, pack=False)
+    b1, _ = run(f32, burst, 1, pack=False)
+    # the same jobs on small resident scenes (20k..200k Gaussians), where
+    # launches rather than arithmetic set the pace: packed vs one launch
+    # sequence per job
+    small_specs = synth.serve_scene_specs(8, n_range=(20_000, 200_000))
+    small = [torch.from_numpy(synth.make_planes(sp)).to(dev) for sp in small_specs]
+    log("serve: burst on small scenes, packed and unpacked")
+    s4, _ = run(small, burst, args.serve_slots)
+    s4n, _ = run(small, burst, args.serve_slots, pack=False)
     return {"workload": "resident scenes n=0.25M..4.9M (log-uniform strata), 50..300 ring views, ratio 0.3..0.9",
             "jobs": len(reqs), "rate_per_s": args.serve_rate, "slots": args.serve_slots,
             "latency_clock": "host: arrival to observed completion",
             "f32": r32, "bf16_f16": r16, "f32_whole_path": r32u,
             "kept_jaccard_bf16_vs_f32": {"min": round(min(jac), 5), "mean": round(float(np.mean(jac)), 5)},
             "burst": {"slots": args.serve_slots, "jobs_per_s": b4["jobs_per_s"], "evals_per_s": b4["evals_per_s"],
-                      "one_slot_jobs_per_s": b1["jobs_per_s"]}}
+                      "unpacked_jobs_per_s": b4n["jobs_per_s"], "one_slot_unpacked_jobs_per_s": b1["jobs_per_s"]},
+            "burst_small_scenes": {"n": "20k..200k", "packed_jobs_per_s": s4["jobs_per_s"],
+                                   "unpacked_jobs_per_s": s4n["jobs_per_s"]}}
 
 
 if __name__ == "__main__":

@@ -23,8 +23,13 @@ from the job's own camera set.  The server
   units, and its launches interleave with the others'.  Jobs with their own
   parameters, or more views than a scene was prepared for, run the whole
   path (stats, prepare, views, select, compact) on the slot's stream;
-* notices completions by polling an event recorded after each job's last
-  call, then frees the slot and the reservation and admits the next jobs.
+* packs small scenes: when two or more small jobs (default parameters, at
+  most ``pack_max_n`` primitives) wait at the head of the queue, up to
+  ``max_pack`` of them go to one slot as one ``refine_prune_batch`` -- a
+  single grouped launch per kernel for all of them;
+* notices completions by polling an event recorded after each launch unit's
+  last call, then frees the slot and the reservation and admits the next
+  jobs.
 
 Each job's results do not depend on what runs beside it: the library's
 reductions have fixed orders (FP64 statistics summed per tile in a fixed
@@ -187,6 +192,7 @@ class Job:
     n_keep: int = 0
     nbytes: int = 0
     on_prepared: bool = False     # scored on its scene's prepared workspace
+    packable: bool = False        # may share a grouped launch with other small jobs
     t_admit: float = 0.0
     t_done: float = 0.0
     slot: int = -1
@@ -215,7 +221,7 @@ class Server:
 
     def __init__(self, device="cuda:0", slots: int = 4, budget_bytes: Optional[int] = None,
                  reserve_bytes: int = 8 << 30, tuner: Optional[Tuner] = None, prepare_scenes: bool = True,
-                 max_views: int = 512):
+                 max_views: int = 512, pack_max_n: int = 1 << 20, max_pack: int = 32):
         import torch
 
         from . import _lib
@@ -234,7 +240,9 @@ class Server:
         self.explicit_budget = budget_bytes
         self.admission = Admission(self._budget(), slots)
         self.queue: collections.deque[Job] = collections.deque()
-        self.running: list[Job] = []
+        self.running: list[tuple] = []           # launch units: (jobs, nbytes, slot, done event)
+        self.pack_max_n = int(pack_max_n)
+        self.max_pack = int(max_pack)
         self.tuner = tuner
         self._next_id = 0
 
@@ -310,6 +318,7 @@ class Server:
         job = Job(self._next_id, scene, cams, float(ratio), prm,
                   time.perf_counter() if t_arrival is None else t_arrival, n=n, n_keep=n_keep)
         job.on_prepared = params is None and scene in self.prepared and V <= self.max_views
+        job.packable = params is None and n <= self.pack_max_n
         job.nbytes = job_bytes(n, V, n_keep, planes.element_size(),
                                api.workspace_size(n, 0 if job.on_prepared else V))
         if not self.admission.fits_ever(job.nbytes):
@@ -360,29 +369,94 @@ class Server:
         job.done_event.record(s)
         job.slot = slot
         job.t_admit = time.perf_counter()
-        self.running.append(job)
+        self.running.append(([job], job.nbytes, slot, job.done_event))
+
+    def _launch_pack(self, jobs: list) -> None:
+        """Prune `jobs` (small, default parameters) with one grouped launch per
+        kernel on one slot."""
+        from . import _lib, api
+        torch = self.torch
+        slot = self.free_slots.popleft()
+        s = self.streams[slot]
+        dev = self.device
+        descs = []
+        with torch.cuda.stream(s):
+            for job in jobs:
+                planes = self.scenes[job.scene]
+                n = job.n
+                job.stats = torch.empty(_lib.STATS_BYTES, dtype=torch.uint8, device=dev)
+                job.scores = torch.empty(max(n, 1), dtype=torch.float32, device=dev)
+                job.keep = torch.empty(max(n, 1), dtype=torch.uint8, device=dev)
+                out_stride = -(-max(job.n_keep, 1) // STRIDE_ALIGN) * STRIDE_ALIGN
+                job.out = torch.empty((N_PLANES, out_stride), dtype=planes.dtype, device=dev)
+                job.index_map = torch.empty(max(job.n_keep, 1), dtype=torch.int32, device=dev)
+                job.n_out = torch.empty(1, dtype=torch.int64, device=dev)
+                descs.append({"planes": planes, "n": n, "cams": job.cams, "ratio": job.ratio, "stats": job.stats,
+                              "scores": job.scores, "keep": job.keep, "out": job.out, "capacity": job.n_keep,
+                              "index_map": job.index_map, "n_out": job.n_out})
+            prm = _lib.default_params()
+            ws = torch.empty(max(api.batch_workspace_size(descs, prm), 1), dtype=torch.uint8, device=dev)
+        s.wait_stream(torch.cuda.current_stream(dev))
+        start = torch.cuda.Event(enable_timing=True)
+        start.record(s)
+        api.refine_prune_batch(descs, ws, prm, stream=s)
+        done = torch.cuda.Event(enable_timing=True)
+        done.record(s)
+        now = time.perf_counter()
+        nbytes = sum(j.nbytes for j in jobs)
+        for job in jobs:
+            job.start_event, job.done_event, job.slot, job.t_admit = start, done, slot, now
+            job.workspace = ws
+        self.running.append((list(jobs), nbytes, slot, done))
 
     def step(self) -> list[Job]:
         """Retire finished jobs, then admit queued ones while they fit.
         Returns the jobs that finished in this step."""
         done = []
         still = []
-        for job in self.running:
-            if job.done_event.query():
-                job.t_done = time.perf_counter()
-                self.admission.release(job.nbytes)
-                self.free_slots.append(job.slot)
-                # the workspace goes back to the allocator, on the job's stream
-                job.workspace = None
-                done.append(job)
+        for unit in self.running:
+            jobs, nbytes, slot, event = unit
+            if event.query():
+                t = time.perf_counter()
+                self.admission.release(nbytes)
+                self.free_slots.append(slot)
+                for job in jobs:
+                    job.t_done = t
+                    # the workspace goes back to the allocator, on the job's stream
+                    job.workspace = None
+                    done.append(job)
             else:
-                still.append(job)
+                still.append(unit)
         self.running = still
-        while self.queue and self.admission.can_admit(self.queue[0].nbytes):
+        while self.queue:
+            pack = self._pack_at_head()
+            if len(pack) >= 2:
+                nbytes = sum(j.nbytes for j in pack)
+                if not self.admission.can_admit(nbytes):
+                    break
+                for _ in pack:
+                    self.queue.popleft()
+                self.admission.admit(nbytes)
+                self._launch_pack(pack)
+                continue
+            if not self.admission.can_admit(self.queue[0].nbytes):
+                break
             job = self.queue.popleft()
             self.admission.admit(job.nbytes)
             self._launch(job)
         return done
+
+    def _pack_at_head(self) -> list:
+        """The packable jobs at the head of the queue, in order, up to
+        max_pack and within the memory left."""
+        pack, nbytes = [], 0
+        room = self.admission.budget - self.admission.in_use
+        for job in self.queue:
+            if not job.packable or len(pack) >= self.max_pack or nbytes + job.nbytes > room:
+                break
+            pack.append(job)
+            nbytes += job.nbytes
+        return pack
 
     def idle(self) -> bool:
         return not self.queue and not self.running

@@ -48,35 +48,42 @@ def _server(scenes, **kw):
     return srv
 
 
-def test_results_same_alone_and_in_the_mix(pool):
+@pytest.mark.parametrize("packing", [False, True])
+def test_results_same_alone_and_in_the_mix(pool, packing):
     """Alone: one slot, every job on the whole path (stats, prepare, views,
-    select, compact).  In the mix: four slots, scenes prepared once, jobs
-    only rebuild camera tables; results must be identical."""
+    select, compact).  In the mix: four slots, everything submitted at once;
+    without packing, scenes prepared once and jobs only rebuild camera
+    tables; with packing, the small jobs share grouped launches.  Results
+    must be identical."""
     scenes, jobs, cams = pool
     alone = []
-    srv1 = _server(scenes, slots=1, prepare_scenes=False)
+    srv1 = _server(scenes, slots=1, prepare_scenes=False, pack_max_n=0)
     srv1_jobs = []
     for sc, V, r in jobs:
         srv1_jobs.append(srv1.submit(sc, cams[V], r))
         (job,) = srv1.drain()
         alone.append(_results(job))
     # in the mix: everything submitted at once, four jobs in flight
-    srv4 = _server(scenes, slots=4)
+    srv4 = _server(scenes, slots=4, pack_max_n=(1 << 20) if packing else 0, max_pack=5)
     subm = [srv4.submit(sc, cams[V], r) for sc, V, r in jobs]
     assert all(j.on_prepared for j in subm) and not any(j.on_prepared for j in srv1_jobs)
     peak = 0
+    largest_unit = 0
     finished = []
     while not srv4.idle():
         finished.extend(srv4.step())
         peak = max(peak, len(srv4.running))
-    assert peak > 1, "jobs never overlapped"
+        largest_unit = max([largest_unit] + [len(u[0]) for u in srv4.running])
+    assert peak > 1, "launch units never overlapped"
+    assert (largest_unit > 1) == packing
     assert sorted(j.id for j in finished) == [j.id for j in subm]
     for j, a in zip(subm, alone):
         b = _results(j)
         for x, y in zip(a[:4], b[:4]):
             np.testing.assert_array_equal(x, y)
         assert a[4] == b[4] == j.n_keep
-    log(f"[serve] {len(jobs)} jobs identical alone and mixed; peak in flight {peak}")
+    log(f"[serve packing={packing}] {len(jobs)} jobs identical alone and mixed; peak units in flight {peak}, "
+        f"largest unit {largest_unit} jobs")
 
 
 def test_admission_budget_bounds_memory(pool):
@@ -95,7 +102,7 @@ def test_admission_budget_bounds_memory(pool):
     while not srv.idle():
         done.extend(srv.step())
         assert srv.admission.in_use <= budget
-        assert sum(j.nbytes for j in srv.running) == srv.admission.in_use
+        assert sum(u[1] for u in srv.running) == srv.admission.in_use
     assert len(done) == len(jobs)
     with pytest.raises(ValueError):
         small = _server(scenes, slots=1, budget_bytes=1000)
