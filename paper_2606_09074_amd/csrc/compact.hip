@@ -9,7 +9,9 @@
 // streams all 59 planes: each row of 256 consecutive primitives is one
 // coalesced load per plane, and the survivors of a row land in one
 // contiguous output range.  Bit copies of 4-byte (FP32) or 2-byte (BF16 /
-// FP16) elements, no arithmetic on the values.
+// FP16) elements, no arithmetic on the values.  The kernel bodies take the
+// tile index, so the grouped launches of a batch (compact_*_batch) run the
+// same code per job.
 #include "refine_internal.hpp"
 
 namespace refine {

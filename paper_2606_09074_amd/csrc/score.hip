@@ -30,22 +30,24 @@
 // so a new camera set only needs new camera records (refine_score_cameras).
 //
 // Direct path (score_direct): one primitive per lane in input order, every
-// pair evaluated.
+// pair evaluated; score_direct_batch runs it for the jobs of a batch in one
+// grouped launch (camera_prep_batch builds their camera records).
 //
-// Binned path: bin_hist / bin_scan / bin_scatter counting-sort the primitives
-// by the Morton code of a 16^3 grid over the centres' bounding box (per-tile
-// LDS histograms, so a crowded cell costs one global atomic per tile, not
-// per primitive) and write each activated primitive as a 64-byte record in
-// cell order.  (A 32^3 grid culls ~10% more pairs but its extra global
-// atomics cost about as much as they save.)  score_binned
-// then gives each wave 64 spatially close primitives: the wave bounds them by
-// a sphere (centre c, radius R) and by their largest scale s_max; each lane
-// tests one view against the sphere, and the ballot of the results is the
-// set of views the wave evaluates.  A view is skipped only when no point of
-// the sphere can pass the near plane or one image edge even with the largest
-// footprint any of its primitives can have, r <= 3 s_max |J|_F (the clamp
-// bounds |J|_F z by kv), inflated by a 1% margin: every skipped pair would
-// have added exactly +0, so both paths give bit-identical scores.
+// Binned path: bin_hist / bin_scan / bin_rank / bin_scatter counting-sort the
+// primitives by the Morton code of a 16^3 grid over the centres' bounding box
+// (per-tile LDS histograms, so a crowded cell costs one global atomic per
+// tile, not per primitive) and write each activated primitive as a 64-byte
+// record in cell order.  (Finer grids cull more pairs but do not fit the
+// per-tile LDS histograms, and one global atomic per primitive costs more
+// than they save.)  score_binned then gives each wave 64 spatially close
+// primitives: the wave bounds their centres by a box and a sphere and their
+// largest scale by s_max; each lane tests one view against those bounds, and
+// the ballot of the results is the set of views the wave evaluates.  A view
+// is skipped only when no point of the bounds can pass the near plane or one
+// image edge even with the largest footprint any of its primitives can
+// have, r <= 3 s_max |J|_F (the clamp bounds |J|_F z by kv), inflated by a 1%
+// margin: every skipped pair would have added exactly +0, so both paths give
+// bit-identical scores.
 #include <type_traits>
 
 #include "refine_internal.hpp"

@@ -17,7 +17,8 @@
 // the tiles before.  Integer arithmetic throughout, so the mask equals a
 // stable sort by (score, index).
 //
-// Launches: init, 3 x (histogram, find), count, mask.
+// Launches: init, 3 x (histogram, find), count, mask -- once per call, or
+// once for all the jobs of a batch (select_*_batch, the same bodies).
 #include "refine_internal.hpp"
 
 namespace refine {

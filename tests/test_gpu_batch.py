@@ -83,3 +83,50 @@ def test_batch_matches_single_scene_calls():
         deq = pl_np if pl_np.dtype == np.float32 else synth.dequantize_bf16_f16(pl_np)
         F, lam, D, lo, hi = oracle_all(deq, cams_np, n=n)
         check_scores(j["scores"].cpu().numpy(), D, lo, hi, what)
+
+
+@pytest.mark.parametrize("mode", [dict(proj_mode=1), dict(proj_mode=2, vis_mode=1), dict(n_sub_views=5, equal_lambda=1)])
+def test_batch_method_switches(mode):
+    """The batch applies the shared parameters like the single calls do."""
+    import torch
+
+    from paper_2606_09074_amd import api
+    dev = torch.device("cuda:0")
+    base = synth.make_planes(synth.SMALL)
+    scenes_np = [np.ascontiguousarray(base[:, a:a + n]) for a, n in ((0, 3000), (5000, 12345), (20000, 777))]
+    cams_np = [synth.ring_cameras(V) for V in (16, 9, 31)]
+    ratios = [0.5, 0.25, 0.75]
+    prm = gpu_params(**mode)
+    res = api.prune_batch([torch.from_numpy(p).to(dev) for p in scenes_np],
+                          [torch.from_numpy(c).to(dev) for c in cams_np], ratios, params=prm)
+    torch.cuda.synchronize()
+    for r, p, c, ratio in zip(res, scenes_np, cams_np, ratios):
+        single = run_gpu(p, c, ratio=ratio, params=gpu_params(score_path=1, **mode))
+        np.testing.assert_array_equal(r["scores"].cpu().numpy().view(np.uint32), single["scores"].view(np.uint32))
+        np.testing.assert_array_equal(r["keep"].cpu().numpy(), single["keep"])
+        F, lam, D, lo, hi = oracle_all(p, c, **mode)
+        check_scores(r["scores"].cpu().numpy(), D, lo, hi, f"batch {mode} n={p.shape[1]}")
+
+
+def test_batch_nonfinite_inputs():
+    """Non-finite inputs are counted per job and give the single-call results."""
+    import torch
+
+    from paper_2606_09074_amd import api
+    dev = torch.device("cuda:0")
+    base = synth.make_planes(synth.SMALL)
+    a = np.ascontiguousarray(base[:, :3000]).copy()
+    b = np.ascontiguousarray(base[:, 3000:9000]).copy()
+    a[0, 7] = np.nan
+    a[4, 100] = np.inf
+    b[12, 5] = -np.inf
+    cams = synth.ring_cameras(16)
+    res = api.prune_batch([torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev)],
+                          [torch.from_numpy(cams).to(dev)] * 2, [0.5, 0.5])
+    torch.cuda.synchronize()
+    for r, p, bad in zip(res, (a, b), (2, 1)):
+        st = api.stats_from_tensor(r["stats"])
+        assert st["n_nonfinite"] == bad
+        single = run_gpu(p, cams, ratio=0.5, params=gpu_params(score_path=1))
+        np.testing.assert_array_equal(r["scores"].cpu().numpy().view(np.uint32), single["scores"].view(np.uint32))
+        np.testing.assert_array_equal(r["keep"].cpu().numpy(), single["keep"])
