@@ -18,6 +18,11 @@ namespace refine {
 
 namespace {
 
+// The aligned scatter splits the 59 planes over this many blocks per tile
+// (grid.y): each recomputes the tile's positions from the mask (4 KB) and
+// copies its planes, so a launch has several blocks per CU to balance.
+constexpr int kCompactPlaneGroups = 4;
+
 __device__ __forceinline__ void compact_count_body(const uint8_t* __restrict__ keep, int n,
                                                           uint32_t* __restrict__ tile_cnt, int blk)
 {
@@ -142,8 +147,8 @@ __global__ __launch_bounds__(kBlock) void compact_scatter(const E* __restrict__ 
 // and a 4-byte aligned mask.  A tile is rows of 16 bytes per lane: 4 rows of
 // 1024 FP32 primitives, or 2 rows of 2048 2-byte primitives; each lane loads
 // its PER consecutive primitives of a row with one 16-byte load per plane.
-// The survivors of 8 KB worth of planes are packed in LDS at their
-// tile-local positions (per-row exclusive scans in index order: the copy
+// The survivors of 16 KB of planes at a time (one FP32 plane or two 2-byte
+// planes of the tile) are packed in LDS at their tile-local positions (per-row exclusive scans in index order: the copy
 // stays stable), then written out with contiguous, fully active stores of 4
 // bytes (two 2-byte elements when `pair_store`: output 4-byte aligned with an
 // even stride).
@@ -171,12 +176,12 @@ __device__ __forceinline__ void compact_scatter_lds_body(const E* __restrict__ i
                                                                 int off_from_scan, int64_t* __restrict__ d_n_out,
                                                                 E* __restrict__ out, int64_t out_stride,
                                                                 int64_t capacity, int32_t* __restrict__ index_map,
-                                                                int pair_store, int blk)
+                                                                int pair_store, int blk, int p_begin, int p_end)
 {
     constexpr int PER = 16 / sizeof(E);               // primitives per lane per row
     constexpr int ROWS = kTile / (PER * kBlock);      // 4 or 2
-    constexpr int kStagePlanes = 8 / sizeof(E);       // 32 KB of LDS
-    const int64_t out0 = tile_start(tile_cnt, tile_off, ntiles, off_from_scan, d_n_out, blk);
+    constexpr int kStagePlanes = 4 / sizeof(E);       // 16 KB of LDS: many blocks per CU
+    const int64_t out0 = tile_start(tile_cnt, tile_off, ntiles, off_from_scan, p_begin == 0 ? d_n_out : nullptr, blk);
     __shared__ uint32_t wtot[ROWS][kWaves];
     __shared__ E stage[kStagePlanes][kTile];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -224,7 +229,7 @@ __device__ __forceinline__ void compact_scatter_lds_body(const E* __restrict__ i
     }
     const int64_t room = capacity - out0;
     const int kept = (int)min((int64_t)tile_cnt[blk], room > 0 ? room : (int64_t)0);
-    if (index_map) {
+    if (index_map && p_begin == 0) {
 #pragma unroll
         for (int r = 0; r < ROWS; ++r) {
             const int i0 = base + r * PER * kBlock + PER * (int)threadIdx.x;
@@ -240,10 +245,10 @@ __device__ __forceinline__ void compact_scatter_lds_body(const E* __restrict__ i
     if (kept == 0) return;   // uniform across the block
     // elements before the first 4-byte boundary of the output range (pair stores)
     const int lead = (sizeof(E) == 2 && pair_store) ? (int)(out0 & 1) : 0;
-    for (int p0 = 0; p0 < kPlanes; p0 += kStagePlanes) {
+    for (int p0 = p_begin; p0 < p_end; p0 += kStagePlanes) {
 #pragma unroll
         for (int q = 0; q < kStagePlanes; ++q) {
-            if (p0 + q >= kPlanes) break;
+            if (p0 + q >= p_end) break;
             const E* src = in + (int64_t)(p0 + q) * in_stride;
 #pragma unroll
             for (int r = 0; r < ROWS; ++r) {
@@ -265,7 +270,7 @@ __device__ __forceinline__ void compact_scatter_lds_body(const E* __restrict__ i
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < kStagePlanes; ++q) {
-            if (p0 + q >= kPlanes) break;
+            if (p0 + q >= p_end) break;
             E* dst = out + (int64_t)(p0 + q) * out_stride + out0;
             if (sizeof(E) == 2 && pair_store) {
                 if (lead && threadIdx.x == 0) dst[0] = stage[q][0];
@@ -290,10 +295,12 @@ __global__ __launch_bounds__(kBlock) void compact_scatter_lds(const E* __restric
                                                                 int off_from_scan, int64_t* __restrict__ d_n_out,
                                                                 E* __restrict__ out, int64_t out_stride,
                                                                 int64_t capacity, int32_t* __restrict__ index_map,
-                                                                int pair_store)
+                                                                int pair_store, int planes_per_group)
 {
+    const int p_begin = (int)blockIdx.y * planes_per_group;
     compact_scatter_lds_body<E>(in, in_stride, n, keep, tile_cnt, tile_off, ntiles, off_from_scan, d_n_out, out,
-                                out_stride, capacity, index_map, pair_store, blockIdx.x);
+                                out_stride, capacity, index_map, pair_store, blockIdx.x, p_begin,
+                                min(p_begin + planes_per_group, kPlanes));
 }
 
 template <class E>
@@ -304,11 +311,15 @@ void launch_compact_t(const E* in, int64_t in_stride, int n, const uint8_t* d_ke
     const bool vec = (reinterpret_cast<uintptr_t>(in) % 16 == 0) && ((in_stride * sizeof(E)) % 16 == 0) &&
                      (reinterpret_cast<uintptr_t>(d_keep) % 4 == 0);
     const int pair_store = (reinterpret_cast<uintptr_t>(out) % 4 == 0) && (out_stride % 2 == 0) ? 1 : 0;
-    if (vec)
-        hipLaunchKernelGGL(compact_scatter_lds<E>, dim3(ntiles), dim3(kBlock), 0, stream, in, in_stride, n, d_keep,
-                           ws.tile_cnt, ws.tile_off, ntiles, from_scan, d_n_out, out, out_stride, capacity,
-                           d_index_map, pair_store);
-    else
+    if (vec) {
+        constexpr int stage = 4 / sizeof(E);   // kStagePlanes of the kernel
+        const int per_group = (kPlanes + kCompactPlaneGroups - 1) / kCompactPlaneGroups;
+        const int planes_per_group = (per_group + stage - 1) / stage * stage;
+        const int groups = (kPlanes + planes_per_group - 1) / planes_per_group;
+        hipLaunchKernelGGL(compact_scatter_lds<E>, dim3(ntiles, groups), dim3(kBlock), 0, stream, in, in_stride, n,
+                           d_keep, ws.tile_cnt, ws.tile_off, ntiles, from_scan, d_n_out, out, out_stride, capacity,
+                           d_index_map, pair_store, planes_per_group);
+    } else
         hipLaunchKernelGGL(compact_scatter<E>, dim3(ntiles), dim3(kBlock), 0, stream, in, in_stride, n, d_keep,
                            ws.tile_cnt, ws.tile_off, ntiles, from_scan, d_n_out, out, out_stride, capacity,
                            d_index_map);
@@ -330,7 +341,7 @@ __device__ __forceinline__ void compact_job_tile(const BatchJob& b, int tile)
     if (b.vec_compact)
         compact_scatter_lds_body<E>(static_cast<const E*>(b.planes), b.stride, b.n, b.keep, b.tile_cnt, nullptr,
                                     ntiles, 0, b.n_out, static_cast<E*>(b.out), b.out_stride, b.capacity,
-                                    b.index_map, b.pair_store, tile);
+                                    b.index_map, b.pair_store, tile, 0, kPlanes);
     else
         compact_scatter_body<E>(static_cast<const E*>(b.planes), b.stride, b.n, b.keep, b.tile_cnt, nullptr,
                                 ntiles, 0, b.n_out, static_cast<E*>(b.out), b.out_stride, b.capacity, b.index_map,

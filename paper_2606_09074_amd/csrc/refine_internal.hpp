@@ -78,8 +78,8 @@ static_assert(sizeof(CullRec) == 32 * sizeof(float), "cull record size");
 // Activated primitive in binned order (64 bytes), written by bin_scatter.
 struct PrimRec {
     float mu[3];
-    float L[9];        // R(q) diag(s), row-major
-    float pre;         // epilogue factor V K / (|V| [sbar^2])
+    float L[9];        // 3 R(q) diag(s), row-major (the 3-sigma factor folded in)
+    float pre;         // epilogue factor V K [/ (9 sbar^2) in COV mode]
     float smax;        // largest scale
     int32_t idx;       // input index
     float pad;

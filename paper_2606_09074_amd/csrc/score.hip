@@ -17,13 +17,18 @@
 //       [r0; r1] / z is the scaled EWA Jacobian times the view rotation (Eq. 14)
 //   A0 = r0 L, A1 = r1 L with L = R(q) diag(s);  a = |A0|^2, b = A0.A1, c = |A1|^2
 //       z^2 Sigma' = [[a, b], [b, c]] as sums of squares (no cancellation for
-//       needle-like primitives, unlike T Sigma T^T in FP32)
+//       needle-like primitives, unlike T Sigma T^T in FP32); the kernels hold
+//       3 L, so their sums are 9 a, 9 b, 9 c
 //   gate: z > z_near, and the centre lies within the 3-sigma radius
 //       r = 3 sqrt(lambda_max(Sigma')) of the image rectangle; with
 //       d = max(|ux| - hw, |uy| - hh) the test d < r reads
-//       d z < 0  or  (d z)^2 < 4.5 (a + c + sqrt((a - c)^2 + 4 b^2))
+//       d z < 0  or  (d z)^2 < 4.5 (a + c + sqrt((a - c)^2 + 4 b^2)),
+//       evaluated without the square root (g = (d z)^2 / 9, u = g - a,
+//       v = g - c: u + v < 0 or u v < b^2)
+//   d z itself is max(|X| - hw z, |Y| - hh z)
 //   projection term: COV (a + c)/(z^2 + eta) (1/sbar^2 applied in the
-//       epilogue), DEPTH 1/(z^2 + eta) (Eq. 17), NONE 1
+//       epilogue, as 1/(9 sbar^2) with the kernels' 3 L), DEPTH
+//       1/(z^2 + eta) (Eq. 17), NONE 1
 // Views are accumulated in view order into one FP32 sum per primitive; the
 // epilogue forms D = (V K [/ sbar^2]) S / |V| (Eq. 20, then Eq. 7).  The
 // binned records hold V K [/ sbar^2], which does not depend on the cameras,
@@ -169,18 +174,22 @@ __device__ inline void activate(const void* __restrict__ planes, int64_t stride,
     } else {
         qw = 1.0f; qx = qy = qz = 0.0f;
     }
-    p.L00 = (1.0f - 2.0f * (qy * qy + qz * qz)) * s0;
-    p.L01 = (2.0f * (qx * qy - qw * qz)) * s1;
-    p.L02 = (2.0f * (qx * qz + qw * qy)) * s2;
-    p.L10 = (2.0f * (qx * qy + qw * qz)) * s0;
-    p.L11 = (1.0f - 2.0f * (qx * qx + qz * qz)) * s1;
-    p.L12 = (2.0f * (qy * qz - qw * qx)) * s2;
-    p.L20 = (2.0f * (qx * qz - qw * qy)) * s0;
-    p.L21 = (2.0f * (qy * qz + qw * qx)) * s1;
-    p.L22 = (1.0f - 2.0f * (qx * qx + qy * qy)) * s2;
+    // L = 3 R(q) diag(s): the factor 3 of the 3-sigma radius rides in L, so
+    // the gate compares (d z)^2 with the projected covariance directly; the
+    // COV epilogue factor below divides the resulting 9 back out
+    const float t0 = 3.0f * s0, t1 = 3.0f * s1, t2 = 3.0f * s2;
+    p.L00 = (1.0f - 2.0f * (qy * qy + qz * qz)) * t0;
+    p.L01 = (2.0f * (qx * qy - qw * qz)) * t1;
+    p.L02 = (2.0f * (qx * qz + qw * qy)) * t2;
+    p.L10 = (2.0f * (qx * qy + qw * qz)) * t0;
+    p.L11 = (1.0f - 2.0f * (qx * qx + qz * qz)) * t1;
+    p.L12 = (2.0f * (qy * qz - qw * qx)) * t2;
+    p.L20 = (2.0f * (qx * qz - qw * qy)) * t0;
+    p.L21 = (2.0f * (qy * qz + qw * qx)) * t1;
+    p.L22 = (1.0f - 2.0f * (qx * qx + qy * qy)) * t2;
     p.S = 0.0f;
     smax = fmaxf(s0, fmaxf(s1, s2));
-    const float sbar2 = (s0 * s0 + s1 * s1 + s2 * s2) * (1.0f / 3.0f);
+    const float ssq = s0 * s0 + s1 * s1 + s2 * s2;   // 3 sbar^2
     const float alpha = 1.0f / (1.0f + __expf(-a[10]));
     const float cr = fmaf(kShC0, a[11], 0.5f), cg = fmaf(kShC0, a[12], 0.5f), cb = fmaf(kShC0, a[13], 0.5f);
     // attribute magnitudes G~ (Eq. 7): two largest scales' product, |DC colour|, alpha
@@ -188,7 +197,7 @@ __device__ inline void activate(const void* __restrict__ planes, int64_t stride,
     const float g_col = sqrtf(cr * cr + cg * cg + cb * cb);
     const float K = (float)st->lambda[0] * g_gem + (float)st->lambda[1] * g_col + (float)st->lambda[2] * alpha;
     pre = (vis_alpha ? alpha : 1.0f) * K;
-    if (proj == REFINE_PROJ_COV) pre = pre / sbar2;
+    if (proj == REFINE_PROJ_COV) pre = pre / (3.0f * ssq);   // 1 / (9 sbar^2): L carries 3
 }
 
 template <int PROJ, class Cam>
@@ -227,14 +236,19 @@ __device__ __forceinline__ void eval_pair(const Cam& c, Prim& p, float eta, floa
         P = q * z;
     else
         P = 1.0f;
-    const float d = fmaxf(fabsf(ux) - c.hw, fabsf(uy) - c.hh);
-    const float dz = d * z;
-    const float e1 = sa - sc;
-    const float w = ss + __builtin_amdgcn_sqrtf(fmaf(e1, e1, 4.0f * sb * sb));
-    const float t = fmaf(w, -4.5f, dz * dz);
-    // dz < 0 or t < 0, as one compare: t is NaN whenever dz is, and fminf
-    // returns the other operand when exactly one is NaN
-    const bool g = (z > z_near) && (fminf(dz, t) < 0.0f);
+    // d z with d = max(|ux| - hw, |uy| - hh) (z > 0 wherever it matters)
+    const float dz = fmaxf(fmaf(-c.hw, z, fabsf(X)), fmaf(-c.hh, z, fabsf(Y)));
+    // With L scaled by 3, sa, sb, sc are 9 a, 9 b, 9 c, and the footprint
+    // test (d z)^2 < 4.5 (a + c + sqrt((a - c)^2 + 4 b^2)) reads
+    // g < (sa + sc)/2 + sqrt(((sa - sc)/2)^2 + sb^2) with g = (d z)^2; with
+    // u = g - sa, v = g - sc it holds iff u + v < 0 or u v < sb^2 (both
+    // sides squared), so no square root is needed
+    const float gq = dz * dz;
+    const float u = gq - sa, v = gq - sc;
+    const float h = fmaf(-sb, sb, u * v);
+    // dz < 0 or u + v < 0 or h < 0, as one compare: the others are NaN
+    // whenever dz is, and fminf returns the other operand when one is NaN
+    const bool g = (z > z_near) && (fminf(dz, fminf(u + v, h)) < 0.0f);
     p.S += g ? P : 0.0f;
 }
 
