@@ -84,6 +84,8 @@ def main() -> int:
     ap.add_argument("--ratio", type=float, default=None)
     ap.add_argument("--score-path", default="auto", choices=["auto", "direct", "binned"],
                     help="refine_score scheduling (results are bit-identical across paths)")
+    ap.add_argument("--records-per-lane", type=int, default=0, choices=[0, 1, 2],
+                    help="binned records each lane of the view loop holds (0: the library's default)")
     ap.add_argument("--storage", default="f32", choices=["f32", "bf16-f16"],
                     help="scene storage: FP32 planes, or BF16 geometry/opacity + FP16 SH (arithmetic is FP32 either way)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -137,6 +139,7 @@ def main() -> int:
     cams = torch.from_numpy(cams_np).to(dev)
     params = _lib.default_params()
     params.score_path = {"auto": _lib.PATH_AUTO, "direct": _lib.PATH_DIRECT, "binned": _lib.PATH_BINNED}[args.score_path]
+    params.records_per_lane = args.records_per_lane
     ws = api.workspace(n, V, dev)
     st = torch.empty(_lib.STATS_BYTES, dtype=torch.uint8, device=dev)
     scores = torch.empty(n, dtype=torch.float32, device=dev)
@@ -237,7 +240,7 @@ def main() -> int:
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
             "data": "synthetic",
             "config": {"workload": spec.name, "n": n, "views": V, "ratio": ratio, "storage": args.storage,
-                       "step": "stats+score+select+compact", "score_path": args.score_path,
+                       "step": "stats+score+select+compact", "score_path": args.score_path, "records_per_lane": args.records_per_lane,
                        "ms_per_prune": round(ms_per_step, 4)},
             "phases_ms": {k: round(v, 4) for k, v in avg.items()},
             "roofline": roofline, "cpu_baseline": cpu, "serving": serving}

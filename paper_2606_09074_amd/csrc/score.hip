@@ -411,28 +411,39 @@ __global__ __launch_bounds__(kBlock) void bin_rank(const void* __restrict__ plan
     }
 }
 
-// Activated primitives written as records at their binned positions.
+// Activated primitives written as records at their binned positions.  The
+// block's records pass through LDS so that each quad of lanes stores one
+// whole 64-byte record (16 records per store instruction instead of 64
+// scattered 16-byte pieces).
 template <int PROJ, int ST>
 __global__ __launch_bounds__(kBlock) void bin_scatter(const void* __restrict__ planes, int64_t stride, int n,
                                                         const refine_stats_t* __restrict__ st, int vis_alpha,
                                                         const uint32_t* __restrict__ dest, PrimRec* __restrict__ recs)
 {
+    __shared__ float4 srec[kBlock][4];
+    __shared__ uint32_t spos[kBlock];
     const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    Prim p;
-    float pre, smax;
-    activate<ST>(planes, stride, i, p, pre, smax, st, PROJ, vis_alpha);
-    const uint32_t pos = dest[i];
-    PrimRec r;
-    r.mu[0] = p.mx; r.mu[1] = p.my; r.mu[2] = p.mz;
-    r.L[0] = p.L00; r.L[1] = p.L01; r.L[2] = p.L02;
-    r.L[3] = p.L10; r.L[4] = p.L11; r.L[5] = p.L12;
-    r.L[6] = p.L20; r.L[7] = p.L21; r.L[8] = p.L22;
-    r.pre = pre;
-    r.smax = smax;
-    r.idx = i;
-    r.pad = 0.0f;
-    if (pos < (uint32_t)n) recs[pos] = r;   // always true: the ranks are a permutation of [0, n)
+    if (i < n) {
+        Prim p;
+        float pre, smax;
+        activate<ST>(planes, stride, i, p, pre, smax, st, PROJ, vis_alpha);
+        spos[threadIdx.x] = dest[i];
+        srec[threadIdx.x][0] = make_float4(p.mx, p.my, p.mz, p.L00);
+        srec[threadIdx.x][1] = make_float4(p.L01, p.L02, p.L10, p.L11);
+        srec[threadIdx.x][2] = make_float4(p.L12, p.L20, p.L21, p.L22);
+        srec[threadIdx.x][3] = make_float4(pre, smax, __int_as_float(i), 0.0f);
+    } else {
+        spos[threadIdx.x] = 0xFFFFFFFFu;
+    }
+    __syncthreads();
+    const int piece = threadIdx.x & 3;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int rr = k * (kBlock / 4) + (threadIdx.x >> 2);
+        const uint32_t pos = spos[rr];
+        // always true for filled slots: the ranks are a permutation of [0, n)
+        if (pos < (uint32_t)n) reinterpret_cast<float4*>(recs + pos)[piece] = srec[rr][piece];
+    }
 }
 
 // May any primitive of the wave's group be visible in this view?  The group's
