@@ -82,8 +82,8 @@ size_t workspace_layout(int64_t n, int32_t n_views, bool score, void* base, Work
     // place depends on the number of views (a workspace prepared for one
     // camera set keeps its binned scene when the tables are rebuilt)
     const size_t o_eval = off;  off += score ? align_up(sizeof(unsigned long long) * kEvalSlots) : 0;
-    const size_t o_ccnt = off;  off += score ? align_up(sizeof(uint32_t) * kCells) : 0;
-    const size_t o_ccur = off;  off += score ? align_up(sizeof(uint32_t) * kCells) : 0;
+    const size_t o_ccnt = off;  off += score ? align_up(sizeof(uint32_t) * kCells * kBinCopies) : 0;
+    const size_t o_ccur = off;  off += score ? align_up(sizeof(uint32_t) * kCells * kBinCopies) : 0;
     const size_t o_dest = off;  off += score ? align_up(sizeof(uint32_t) * (size_t)n) : 0;
     const size_t o_recs = off;  off += score ? align_up(sizeof(PrimRec) * (size_t)n) : 0;
     const size_t o_cams = off;  off += score ? align_up(sizeof(CamRec) * nv) : 0;

@@ -90,6 +90,7 @@ constexpr int kEvalSlots = 64;                     // counters the evaluated pai
 
 constexpr int kCellBits = 4;                       // per axis
 constexpr int kCells = 1 << (3 * kCellBits);       // 4096 Morton cells (16 KB of LDS counters)
+constexpr int kBinCopies = 8;                      // global cell counters per cell (one per block residue)
 
 struct Workspace {
     SelectState* sel;
@@ -100,8 +101,8 @@ struct Workspace {
     // refine_score only:
     CamRec* cams;            // [n_views]
     CullRec* culls;          // [n_views]
-    uint32_t* cell_cnt;      // [kCells]
-    uint32_t* cell_cur;      // [kCells]
+    uint32_t* cell_cnt;      // [kBinCopies][kCells]
+    uint32_t* cell_cur;      // [kBinCopies][kCells]
     uint32_t* dest;          // [n] binned position of each primitive
     PrimRec* recs;           // [n]
     unsigned long long* evaluated;   // [kEvalSlots] pairs evaluated by the last view loop

@@ -134,7 +134,7 @@ __global__ __launch_bounds__(kBlock) void camera_prep(const float* __restrict__ 
                                                         CullRec* __restrict__ cull, uint32_t* __restrict__ cell_cnt)
 {
     const int j = blockIdx.x * kBlock + threadIdx.x;
-    if (cell_cnt && j < kCells) cell_cnt[j] = 0u;
+    if (cell_cnt && j < kCells * kBinCopies) cell_cnt[j] = 0u;
     if (j < nv) camera_prep_body(cams, n_views, nv, clamp_k, out, cull, j);
 }
 
@@ -329,7 +329,10 @@ __device__ inline uint32_t cell_of(float x, float y, float z, const refine_stats
 // tile counts its cells in LDS and touches the global cell arrays once per
 // occupied cell, in cell order (consecutive lanes hit consecutive counters,
 // so the atomics coalesce); global atomics are memory transactions here, so
-// their number, not the LDS work, sets the cost.
+// their number, not the LDS work, sets the cost.  The global counters come
+// in kBinCopies copies (tile t uses copy t mod kBinCopies, copy-major so the
+// lanes stay coalesced), which divides the atomics per address by 8; a
+// cell's range holds copy 0's primitives, then copy 1's, and so on.
 constexpr int kCellsPerThread = kCells / kBlock;   // 16
 
 // Morton cell of primitive i's centre.
@@ -357,17 +360,51 @@ __global__ __launch_bounds__(kBlock) void bin_hist(const void* __restrict__ plan
         if (i < n) atomicAdd(&h[cell_of_prim<ST>(planes, stride, i, st)], 1u);
     }
     __syncthreads();
+    const int copy = blockIdx.x % kBinCopies;
 #pragma unroll
     for (int j = 0; j < kCellsPerThread; ++j) {
         const int c = j * kBlock + (int)threadIdx.x;
-        if (h[c]) atomicAdd(&cnt[c], h[c]);
+        if (h[c]) atomicAdd(&cnt[copy * kCells + c], h[c]);
     }
 }
 
-// Cell offsets: exclusive scan of the counts (one block).
+// Cell offsets (one block): each cell's range starts at the exclusive scan of
+// the cell totals, and the range of copy k of the cell after copies 0..k-1.
 __global__ __launch_bounds__(kScanThreads) void bin_scan(const uint32_t* __restrict__ cnt, uint32_t* __restrict__ cur)
 {
-    block_exclusive_scan(cnt, cur, kCells);
+    constexpr int kPer = kCells / kScanThreads;   // 4 cells per thread
+    static_assert(kPer == 4, "one 16-byte load per copy");
+    __shared__ uint32_t wave_tot[kScanThreads / 64];
+    uint32_t c8[kPer][kBinCopies];
+    uint32_t local = 0;
+#pragma unroll
+    for (int k = 0; k < kBinCopies; ++k) {
+        const uint4 a = reinterpret_cast<const uint4*>(cnt + k * kCells)[threadIdx.x];
+        c8[0][k] = a.x; c8[1][k] = a.y; c8[2][k] = a.z; c8[3][k] = a.w;
+        local += a.x + a.y + a.z + a.w;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t incl = local;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += y;
+    }
+    if (lane == 63) wave_tot[wave] = incl;
+    __syncthreads();
+    uint32_t run = incl - local;
+    for (int w = 0; w < wave; ++w) run += wave_tot[w];
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        uint32_t o[kBinCopies];
+#pragma unroll
+        for (int k = 0; k < kBinCopies; ++k) {
+            o[k] = run;
+            run += c8[j][k];
+        }
+#pragma unroll
+        for (int k = 0; k < kBinCopies; ++k) cur[k * kCells + threadIdx.x * kPer + j] = o[k];
+    }
 }
 
 // Counting-sort ranks: each tile reserves one output range per occupied cell
@@ -395,11 +432,12 @@ __global__ __launch_bounds__(kBlock) void bin_rank(const void* __restrict__ plan
     __syncthreads();
     // all reservations of this thread are issued before any result is used
     uint32_t got[kCellsPerThread];
+    const int copy = blockIdx.x % kBinCopies;
 #pragma unroll
     for (int j = 0; j < kCellsPerThread; ++j) {
         const int c = j * kBlock + (int)threadIdx.x;
         const uint32_t m = h[c];
-        got[j] = m ? atomicAdd(&cur[c], m) : 0u;
+        got[j] = m ? atomicAdd(&cur[copy * kCells + c], m) : 0u;
     }
 #pragma unroll
     for (int j = 0; j < kCellsPerThread; ++j) h[j * kBlock + (int)threadIdx.x] = got[j];
@@ -665,7 +703,7 @@ hipError_t launch_score_prepare(const void* planes, int st, int64_t stride, int6
 {
     const int nv = views_of(prm, n_views);
     const bool binned = n > 0 && binned_path(prm, n);
-    const int threads = binned ? (nv > kCells ? nv : kCells) : nv;
+    const int threads = binned ? (nv > kCells * kBinCopies ? nv : kCells * kBinCopies) : nv;
     hipLaunchKernelGGL(camera_prep, dim3((threads + kBlock - 1) / kBlock), dim3(kBlock), 0, stream, d_cams, n_views, nv,
                        (float)prm.clamp_k, ws.cams, ws.culls, binned ? ws.cell_cnt : nullptr);
     if (!binned) return hipGetLastError();
