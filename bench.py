@@ -32,6 +32,9 @@ if ROOT not in sys.path:
 FLOP_PER_PAIR = {0: 103, 1: 25, 2: 22}
 BYTES_PER_PRIM = 14 * 4 + 4
 PEAK_FP32_TFLOPS = 157.3      # MI355X dense FP32 vector, vendor figure
+# VALU issue: 256 CU x 4 SIMD x 2.4 GHz / 2 cycles per wave64 FP32 instruction
+# (the same hardware rate that gives 157.3 TFLOP/s with FMAs)
+PEAK_VALU_GINSTS = 1228.8
 PEAK_HBM_GBS = 8000.0
 
 
@@ -53,26 +56,31 @@ def kernel_sources_sha256() -> str:
     return h.hexdigest()
 
 
-def profiled_traffic(kernel: str, workload: str):
-    """HBM bytes per launch of `kernel` on `workload` from the committed
-    counter summary (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, see
-    profiles/copy-1GiB_traffic-calibration.md), or None when there is none or
+def profiled_counters(kernel: str, workload: str) -> dict:
+    """Per-launch counter figures of `kernel` on `workload` from the committed
+    summary profiles/<kernel>_<workload>_traffic.md: HBM bytes (FETCH_SIZE x
+    2.0 + WRITE_SIZE x 1.0, see profiles/copy-1GiB_traffic-calibration.md)
+    and VALU instructions (SQ_INSTS_VALU).  Empty when there is no summary or
     the kernel sources changed after it was taken."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.md")
     if not os.path.exists(path):
-        return None
+        return {}
     fields = {}
     with open(path) as f:
         for line in f:
-            if ":" in line and line.split(":", 1)[0].strip() in ("sources_sha256", "hbm_bytes_per_launch"):
+            if ":" in line:
                 k, v = line.split(":", 1)
-                fields[k.strip()] = v.strip().strip("`")
-    if fields.get("sources_sha256") != kernel_sources_sha256():
-        return None
-    try:
-        return int(fields["hbm_bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
+                if k.strip() in ("sources_sha256", "hbm_bytes_per_launch", "valu_insts_per_launch"):
+                    fields[k.strip()] = v.strip().strip("`")
+    if fields.pop("sources_sha256", None) != kernel_sources_sha256():
+        return {}
+    out = {}
+    for k, v in fields.items():
+        try:
+            out[k] = int(v)
+        except ValueError:
+            pass
+    return out
 
 
 def main() -> int:
@@ -210,10 +218,17 @@ def main() -> int:
     t_views = avg["views"] / 1e3
     achieved_tflops = FLOP_PER_PAIR[params.proj_mode] * n_eval / t_views / 1e12
     kname = "score_binned" if n_eval < n * V else "score_direct"
-    traffic = profiled_traffic(kname, spec.name) if params.proj_mode == 0 else None
+    counters = profiled_counters(kname, spec.name) if params.proj_mode == 0 else {}
+    traffic = counters.get("hbm_bytes_per_launch")
+    valu = counters.get("valu_insts_per_launch")
+    valu_issue = None
+    if valu:
+        rate = valu / t_views / 1e9
+        valu_issue = {"insts_per_launch": valu, "achieved": round(rate, 1), "peak": PEAK_VALU_GINSTS,
+                      "unit": "G wave-instructions/s", "frac": round(rate / PEAK_VALU_GINSTS, 4)}
     roofline = {"bound": "alu", "kernel": kname,
                 "achieved": round(achieved_tflops, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved_tflops / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
+                "frac": round(achieved_tflops / PEAK_FP32_TFLOPS, 4), "traffic": traffic, "valu_issue": valu_issue,
                 "flop_per_pair": FLOP_PER_PAIR[params.proj_mode], "pairs_evaluated": n_eval,
                 "pairs_total": n * V, "views_ms": round(avg["views"], 4), "prepare_ms": round(avg["prepare"], 4)}
     cpu = None

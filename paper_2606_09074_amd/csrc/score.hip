@@ -509,6 +509,19 @@ __device__ inline bool cull_pass(const CullRec& q, float cx, float cy, float cz,
     return ok;
 }
 
+// The staged evaluation constants of one view (five LDS float4 reads).
+__device__ __forceinline__ void load_cam(const float4* __restrict__ r, CamEval& c)
+{
+    const float4 r0 = r[0], r1 = r[1], r2 = r[2], r3 = r[3], r4 = r[4];
+    c.px[0] = r0.x; c.px[1] = r0.y; c.px[2] = r0.z; c.px[3] = r0.w;
+    c.py[0] = r1.x; c.py[1] = r1.y; c.py[2] = r1.z; c.py[3] = r1.w;
+    c.pz[0] = r2.x; c.pz[1] = r2.y; c.pz[2] = r2.z; c.pz[3] = r2.w;
+    c.cx0 = r3.x; c.cx1 = r3.y; c.cy0 = r3.z; c.cy1 = r3.w;
+    c.hw = r4.x; c.hh = r4.y;
+}
+
+constexpr int kViewChunk = 256;   // views staged in LDS at a time (20 KB)
+
 // PPL binned records per lane: a wave owns a group of 64 PPL consecutive
 // records (lane l holds records l, l + 64, ...), bounds them by one sphere and
 // evaluates each visible view for all of them, so the per-view overhead
@@ -570,47 +583,32 @@ __global__ __launch_bounds__(kBlock) void score_binned(const PrimRec* __restrict
     const float sg = wave_max(smax);
     // a non-finite bound (non-finite input) disables culling for this group
     const bool no_cull = !(rm < INFINITY) || !(sg < INFINITY) || !(ca < INFINITY);
-    // the evaluation constants of the views this wave evaluates, staged in
-    // LDS so that every camera operand of the pair arithmetic is a vector
-    // register (an instruction may read only one scalar register)
-    __shared__ float4 stage[kWaves][64 * kStageVec];
-    float4* const my = stage[threadIdx.x >> 6];
+    // the evaluation constants of up to kViewChunk views, loaded into LDS by
+    // the whole block, so that every camera operand of the pair arithmetic
+    // is a vector register (an instruction may read only one scalar register)
+    __shared__ float4 table[kViewChunk * kStageVec];
     uint32_t n_eval = 0;
-    for (int v0 = 0; v0 < nv; v0 += 64) {
-        const int v = v0 + lane;
-        bool vis = false;
-        if (v < nv) vis = no_cull || cull_pass(culls[v], cx, cy, cz, hx, hy, hz, rm, sg, ca, z_near);
-        const uint64_t m = __ballot(vis);
-        if (vis) {
-            // visible views packed in increasing view order
-            const float4* src = reinterpret_cast<const float4*>(cams + v);
-            float4* dst = my + lanes_below(m) * kStageVec;
+    for (int c0 = 0; c0 < nv; c0 += kViewChunk) {
+        const int cn = min(kViewChunk, nv - c0);
+        __syncthreads();   // the previous chunk's reads are done
+        for (int t = threadIdx.x; t < cn * kStageVec; t += kBlock)
+            table[t] = reinterpret_cast<const float4*>(cams + c0 + t / kStageVec)[t % kStageVec];
+        __syncthreads();
+        for (int v0 = c0; v0 < c0 + cn; v0 += 64) {
+            const int v = v0 + lane;
+            bool vis = false;
+            if (v < nv) vis = no_cull || cull_pass(culls[v], cx, cy, cz, hx, hy, hz, rm, sg, ca, z_near);
+            uint64_t m = __ballot(vis);
+            n_eval += (uint32_t)__popcll(m);
+            while (m != 0ull) {
+                const int b = __builtin_ctzll(m);
+                m &= m - 1ull;
+                CamEval c;
+                load_cam(table + (v0 - c0 + b) * kStageVec, c);
 #pragma unroll
-            for (int k = 0; k < kStageVec; ++k) dst[k] = src[k];
+                for (int k = 0; k < PPL; ++k) eval_pair<PROJ>(c, p[k], eta, z_near);
+            }
         }
-        // the writes above precede the reads below (LDS requests of one wave
-        // complete in order; the fences keep the compiler from moving them)
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        const int cnt = __popcll(m);
-        n_eval += (uint32_t)cnt;
-        for (int j = 0; j < cnt; ++j) {
-            CamEval c;
-            const float4* r = my + j * kStageVec;
-            const float4 r0 = r[0], r1 = r[1], r2 = r[2], r3 = r[3], r4 = r[4];
-            c.px[0] = r0.x; c.px[1] = r0.y; c.px[2] = r0.z; c.px[3] = r0.w;
-            c.py[0] = r1.x; c.py[1] = r1.y; c.py[2] = r1.z; c.py[3] = r1.w;
-            c.pz[0] = r2.x; c.pz[1] = r2.y; c.pz[2] = r2.z; c.pz[3] = r2.w;
-            c.cx0 = r3.x; c.cx1 = r3.y; c.cy0 = r3.z; c.cy1 = r3.w;
-            c.hw = r4.x; c.hh = r4.y;
-#pragma unroll
-            for (int k = 0; k < PPL; ++k) eval_pair<PROJ>(c, p[k], eta, z_near);
-        }
-        // every lane's reads of this batch precede the next batch's writes
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     }
 #pragma unroll
     for (int k = 0; k < PPL; ++k)
