@@ -75,6 +75,11 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2606_09074_amd.build` "
                            "(there is no CPU fallback)")
+    # torch ships its own HIP runtime under the same soname (libamdhip64.so.7)
+    # as the system one the library links; whichever is loaded first serves
+    # the whole process, so torch is loaded first and the library's HIP calls
+    # share torch's runtime, devices and streams
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     P = ctypes.c_void_p
     i64, i32, sz = ctypes.c_int64, ctypes.c_int32, ctypes.c_size_t
