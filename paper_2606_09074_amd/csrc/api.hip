@@ -85,9 +85,15 @@ size_t workspace_layout(int64_t n, int32_t n_views, bool score, void* base, Work
     const size_t o_ccnt = off;  off += score ? align_up(sizeof(uint32_t) * kCells * kBinCopies) : 0;
     const size_t o_ccur = off;  off += score ? align_up(sizeof(uint32_t) * kCells * kBinCopies) : 0;
     const size_t o_dest = off;  off += score ? align_up(sizeof(uint32_t) * (size_t)n) : 0;
+    const size_t ng = (size_t)num_groups(n, kGroup);
     const size_t o_recs = off;  off += score ? align_up(sizeof(PrimRec) * (size_t)n) : 0;
+    const size_t o_gbnd = off;  off += score ? align_up(sizeof(GroupBound) * ng) : 0;
+    const size_t o_gord = off;  off += score ? align_up(sizeof(int32_t) * ng) : 0;
+    const size_t o_gcnt = off;  off += score ? align_up(sizeof(uint32_t) * ng) : 0;
+    const size_t o_gaux = off;  off += score ? align_up(sizeof(uint32_t) * 2 * kOrderBuckets) : 0;
     const size_t o_cams = off;  off += score ? align_up(sizeof(CamRec) * nv) : 0;
     const size_t o_cull = off;  off += score ? align_up(sizeof(CullRec) * nv) : 0;
+    const size_t o_gmsk = off;  off += score ? align_up(sizeof(uint64_t) * ng * ((nv + 63) / 64)) : 0;
     if (base && ws) {
         char* b = static_cast<char*>(base);
         ws->sel = reinterpret_cast<SelectState*>(b + o_sel);
@@ -101,6 +107,11 @@ size_t workspace_layout(int64_t n, int32_t n_views, bool score, void* base, Work
         ws->cell_cur = score ? reinterpret_cast<uint32_t*>(b + o_ccur) : nullptr;
         ws->dest = score ? reinterpret_cast<uint32_t*>(b + o_dest) : nullptr;
         ws->recs = score ? reinterpret_cast<PrimRec*>(b + o_recs) : nullptr;
+        ws->gbound = score ? reinterpret_cast<GroupBound*>(b + o_gbnd) : nullptr;
+        ws->gorder = score ? reinterpret_cast<int32_t*>(b + o_gord) : nullptr;
+        ws->gcount = score ? reinterpret_cast<uint32_t*>(b + o_gcnt) : nullptr;
+        ws->gaux = score ? reinterpret_cast<uint32_t*>(b + o_gaux) : nullptr;
+        ws->gmask = score ? reinterpret_cast<uint64_t*>(b + o_gmsk) : nullptr;
         ws->evaluated = score ? reinterpret_cast<unsigned long long*>(b + o_eval) : nullptr;
     }
     return off;

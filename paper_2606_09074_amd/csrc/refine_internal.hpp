@@ -75,16 +75,34 @@ struct CullRec {
 };
 static_assert(sizeof(CullRec) == 32 * sizeof(float), "cull record size");
 
-// Activated primitive in binned order (64 bytes), written by bin_scatter.
+// Activated primitive in binned order (64 bytes), written by bin_scatter;
+// the centre and largest scale come first, so the group-bounds pass reads
+// only the first 16 bytes.
 struct PrimRec {
     float mu[3];
+    float smax;        // largest scale
     float L[9];        // 3 R(q) diag(s), row-major (the 3-sigma factor folded in)
     float pre;         // epilogue factor V K [/ (9 sbar^2) in COV mode]
-    float smax;        // largest scale
     int32_t idx;       // input index
     float pad;
 };
 static_assert(sizeof(PrimRec) == 64, "primitive record size");
+
+// Conservative bounds of a group of kGroup consecutive binned records: the
+// box c +- h and the sphere (c, rm) hold every centre (both inflated by the
+// culling margin), sg is the group's largest scale.
+struct GroupBound {
+    float c[3];
+    float h[3];
+    float rm;
+    float sg;
+};
+static_assert(sizeof(GroupBound) == 32, "group bound size");
+
+constexpr int kGroup = 64;         // records per group: one per lane of a wave
+constexpr int kOrderBuckets = 32;  // work classes of the group order (most views first)
+
+__host__ __device__ inline int64_t num_groups(int64_t n, int per) { return (n + per - 1) / per; }
 
 constexpr int kEvalSlots = 64;                     // counters the evaluated pairs are spread over
 
@@ -104,7 +122,12 @@ struct Workspace {
     uint32_t* cell_cnt;      // [kBinCopies][kCells]
     uint32_t* cell_cur;      // [kBinCopies][kCells]
     uint32_t* dest;          // [n] binned position of each primitive
-    PrimRec* recs;           // [n]
+    PrimRec* recs;           // [n] activated primitives in binned order
+    GroupBound* gbound;      // [num_groups(n, kGroup)]
+    int32_t* gorder;         // [num_groups(n, kGroup)] group order of the view loop
+    uint32_t* gcount;        // [num_groups(n, kGroup)] views each view-loop group evaluates
+    uint32_t* gaux;          // [2][kOrderBuckets] work-class counts and cursors
+    uint64_t* gmask;         // [num_groups(n, kGroup)][ceil(n_views / 64)] views each group evaluates
     unsigned long long* evaluated;   // [kEvalSlots] pairs evaluated by the last view loop
 };
 

@@ -38,21 +38,25 @@
 // pair evaluated; score_direct_batch runs it for the jobs of a batch in one
 // grouped launch (camera_prep_batch builds their camera records).
 //
-// Binned path: bin_hist / bin_scan / bin_rank / bin_scatter counting-sort the
-// primitives by the Morton code of a 16^3 grid over the centres' bounding box
-// (per-tile LDS histograms, so a crowded cell costs one global atomic per
-// tile, not per primitive) and write each activated primitive as a 64-byte
-// record in cell order.  (Finer grids cull more pairs but do not fit the
-// per-tile LDS histograms, and one global atomic per primitive costs more
-// than they save.)  score_binned then gives each wave 64 spatially close
-// primitives: the wave bounds their centres by a box and a sphere and their
-// largest scale by s_max; each lane tests one view against those bounds, and
-// the ballot of the results is the set of views the wave evaluates.  A view
-// is skipped only when no point of the bounds can pass the near plane or one
-// image edge even with the largest footprint any of its primitives can
-// have, r <= 3 s_max |J|_F (the clamp bounds |J|_F z by kv), inflated by a 1%
-// margin: every skipped pair would have added exactly +0, so both paths give
-// bit-identical scores.
+// Binned path, preparation (camera independent): bin_hist / bin_scan /
+// bin_rank / bin_scatter counting-sort the primitives by the Morton code of a
+// 16^3 grid over the centres' bounding box (per-tile LDS histograms, so a
+// crowded cell costs one global atomic per tile, not per primitive) and write
+// each activated primitive as a record in cell order; group_bounds bounds
+// each group of 64 consecutive records by a box and a sphere about its
+// centres and by its largest scale s_max.  (Finer grids cull more pairs but
+// do not fit the per-tile LDS histograms, and one global atomic per primitive
+// costs more than they save.)
+//
+// Binned path, per camera set: cull_groups gives every group the set of
+// views it evaluates: a view is dropped only when no point of the group's
+// bounds can pass the near plane or one image edge even with the largest
+// footprint any of its primitives can have, r <= 3 s_max |J|_F (the clamp
+// bounds |J|_F z by kv), inflated by a 1% margin, so every dropped pair
+// would have added exactly +0 and both paths give bit-identical scores.
+// place_groups orders the groups by how many views they keep (most first,
+// so no long group runs alone at the end), and score_binned gives each wave
+// one group and evaluates its kept views in increasing view order.
 #include <type_traits>
 
 #include "refine_internal.hpp"
@@ -466,10 +470,11 @@ __global__ __launch_bounds__(kBlock) void bin_scatter(const void* __restrict__ p
         float pre, smax;
         activate<ST>(planes, stride, i, p, pre, smax, st, PROJ, vis_alpha);
         spos[threadIdx.x] = dest[i];
-        srec[threadIdx.x][0] = make_float4(p.mx, p.my, p.mz, p.L00);
-        srec[threadIdx.x][1] = make_float4(p.L01, p.L02, p.L10, p.L11);
-        srec[threadIdx.x][2] = make_float4(p.L12, p.L20, p.L21, p.L22);
-        srec[threadIdx.x][3] = make_float4(pre, smax, __int_as_float(i), 0.0f);
+        srec[threadIdx.x][0] = make_float4(p.mx, p.my, p.mz, smax);
+        srec[threadIdx.x][1] = make_float4(p.L00, p.L01, p.L02, p.L10);
+        srec[threadIdx.x][2] = make_float4(p.L11, p.L12, p.L20, p.L21);
+        srec[threadIdx.x][3] = make_float4(p.L22, pre, __int_as_float(i), 0.0f);
+        static_assert(offsetof(PrimRec, L) == 16 && offsetof(PrimRec, idx) == 56, "record layout");
     } else {
         spos[threadIdx.x] = 0xFFFFFFFFu;
     }
@@ -481,6 +486,81 @@ __global__ __launch_bounds__(kBlock) void bin_scatter(const void* __restrict__ p
         const uint32_t pos = spos[rr];
         // always true for filled slots: the ranks are a permutation of [0, n)
         if (pos < (uint32_t)n) reinterpret_cast<float4*>(recs + pos)[piece] = srec[rr][piece];
+    }
+}
+
+// Bounds of each group of kGroup consecutive binned records (16 lanes per
+// group, 4 records per lane; records past the end repeat the last one): the
+// box and sphere of the centres, inflated by the culling margin plus a
+// relative slack, and the largest scale.  They do not depend on the cameras.
+constexpr int kBoundLanes = 16;
+constexpr int kBoundPer = kGroup / kBoundLanes;   // 4
+
+__device__ inline float seg_min(float x)
+{
+#pragma unroll
+    for (int o = kBoundLanes / 2; o > 0; o >>= 1) x = fminf(x, __shfl_xor(x, o, kBoundLanes));
+    return x;
+}
+
+__device__ inline float seg_max(float x)
+{
+#pragma unroll
+    for (int o = kBoundLanes / 2; o > 0; o >>= 1) x = fmaxf(x, __shfl_xor(x, o, kBoundLanes));
+    return x;
+}
+
+__global__ __launch_bounds__(kBlock) void group_bounds(const PrimRec* __restrict__ recs, int n,
+                                                         GroupBound* __restrict__ gb, int ngroups,
+                                                         uint32_t* __restrict__ aux)
+{
+    if (blockIdx.x == 0 && threadIdx.x < kOrderBuckets) aux[threadIdx.x] = 0u;   // for the first view loop
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    const int g = t / kBoundLanes, sl = t % kBoundLanes;
+    const bool ok = g < ngroups;   // whole 16-lane segments
+    float4 r[kBoundPer];
+#pragma unroll
+    for (int k = 0; k < kBoundPer; ++k) {
+        const int j = ok ? min(g * kGroup + k * kBoundLanes + sl, n - 1) : 0;
+        r[k] = *reinterpret_cast<const float4*>(recs + j);   // centre, s_max
+    }
+    float lo[3] = {r[0].x, r[0].y, r[0].z}, hi[3] = {r[0].x, r[0].y, r[0].z}, sg = r[0].w;
+#pragma unroll
+    for (int k = 1; k < kBoundPer; ++k) {
+        lo[0] = fminf(lo[0], r[k].x); hi[0] = fmaxf(hi[0], r[k].x);
+        lo[1] = fminf(lo[1], r[k].y); hi[1] = fmaxf(hi[1], r[k].y);
+        lo[2] = fminf(lo[2], r[k].z); hi[2] = fmaxf(hi[2], r[k].z);
+        sg = fmaxf(sg, r[k].w);
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = seg_min(lo[a]);
+        hi[a] = seg_max(hi[a]);
+    }
+    sg = seg_max(sg);
+    const float cx = 0.5f * (lo[0] + hi[0]);
+    const float cy = 0.5f * (lo[1] + hi[1]);
+    const float cz = 0.5f * (lo[2] + hi[2]);
+    float d2 = 0.0f;
+#pragma unroll
+    for (int k = 0; k < kBoundPer; ++k) {
+        const float dx = r[k].x - cx, dy = r[k].y - cy, dz = r[k].z - cz;
+        d2 = fmaxf(d2, dx * dx + dy * dy + dz * dz);
+    }
+    d2 = seg_max(d2);
+    if (ok && sl == 0) {
+        const float ca = fabsf(cx) + fabsf(cy) + fabsf(cz);
+        const float abs_m = 1e-4f * (ca + 1.0f);
+        GroupBound b;
+        b.c[0] = cx;
+        b.c[1] = cy;
+        b.c[2] = cz;
+        b.h[0] = 0.5f * (hi[0] - lo[0]) * kCullMargin + abs_m;
+        b.h[1] = 0.5f * (hi[1] - lo[1]) * kCullMargin + abs_m;
+        b.h[2] = 0.5f * (hi[2] - lo[2]) * kCullMargin + abs_m;
+        b.rm = sqrtf(d2) * kCullMargin + abs_m;
+        b.sg = sg;
+        gb[g] = b;
     }
 }
 
@@ -504,7 +584,9 @@ __device__ inline bool cull_pass(const CullRec& q, float cx, float cy, float cz,
         const float val = fmaf(q.side[s][0], cx, fmaf(q.side[s][1], cy, fmaf(q.side[s][2], cz, q.side[s][3])));
         const float slack = 1e-4f * (q.nn[s] * (ca + 1.0f) + fabsf(q.side[s][3]));
         const float sup = support(q.side[s][0], q.side[s][1], q.side[s][2], q.nn[s], hx, hy, hz, rm);
-        ok = ok && (val + sup + sg * q.kv3 + slack > 0.0f);
+        // no short circuit: all five tests and the loads of the record they
+        // read are independent, so they issue together
+        ok = ok & (val + sup + sg * q.kv3 + slack > 0.0f);
     }
     return ok;
 }
@@ -522,67 +604,194 @@ __device__ __forceinline__ void load_cam(const float4* __restrict__ r, CamEval& 
 
 constexpr int kViewChunk = 256;   // views staged in LDS at a time (20 KB)
 
-// PPL binned records per lane: a wave owns a group of 64 PPL consecutive
-// records (lane l holds records l, l + 64, ...), bounds them by one sphere and
-// evaluates each visible view for all of them, so the per-view overhead
-// (record loads, loop control) is shared by PPL pairs.
+// Bounds of view-loop group G (PPL groups of kGroup records), merged from
+// the PPL bound records it covers: the union box, and a sphere about the
+// union box's centre holding every member sphere (conservative).
+template <int PPL>
+__device__ inline GroupBound loop_group_bound(const GroupBound* __restrict__ gb, int ngroups64, int G)
+{
+    GroupBound b = gb[G * PPL];
+    if (PPL == 1) return b;
+    float lo[3], hi[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = b.c[a] - b.h[a];
+        hi[a] = b.c[a] + b.h[a];
+    }
+    float sg = b.sg;
+#pragma unroll
+    for (int k = 1; k < PPL; ++k) {
+        if (G * PPL + k >= ngroups64) break;
+        const GroupBound o = gb[G * PPL + k];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = fminf(lo[a], o.c[a] - o.h[a]);
+            hi[a] = fmaxf(hi[a], o.c[a] + o.h[a]);
+        }
+        sg = fmaxf(sg, o.sg);
+    }
+    GroupBound m;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        m.c[a] = 0.5f * (lo[a] + hi[a]);
+        m.h[a] = 0.5f * (hi[a] - lo[a]);
+    }
+    float rm = 0.0f;
+#pragma unroll
+    for (int k = 0; k < PPL; ++k) {
+        if (G * PPL + k >= ngroups64) break;
+        const GroupBound o = gb[G * PPL + k];
+        const float dx = o.c[0] - m.c[0], dy = o.c[1] - m.c[1], dz = o.c[2] - m.c[2];
+        rm = fmaxf(rm, sqrtf(dx * dx + dy * dy + dz * dz) * kCullMargin + o.rm);
+    }
+    m.rm = rm;
+    m.sg = sg;
+    return m;
+}
+
+// Work class of a group that evaluates `cnt` of nv views: 0 for the most.
+__device__ inline int work_class(uint32_t cnt, int nv)
+{
+    const int c = (int)(((uint64_t)cnt * kOrderBuckets) / (uint64_t)(nv + 1));
+    return kOrderBuckets - 1 - min(c, kOrderBuckets - 1);
+}
+
+// Clears the pair counters when the view loop does not run (n = 0).
+__global__ void views_init(unsigned long long* __restrict__ evaluated)
+{
+    if (threadIdx.x < kEvalSlots) evaluated[threadIdx.x] = 0ull;
+}
+
+// The views each view-loop group evaluates, as 64-bit masks: a block takes
+// 64 groups (their bounds staged in LDS), each wave 16 of them; lane l holds
+// the culling record of view 64 b + l in registers and tests it against
+// each group in turn.  A view is dropped only when no point of the group's
+// bounds can pass the near plane or one image edge even with the largest
+// footprint any of its primitives can have.  Also counts each group's views
+// into the block's work classes.
+constexpr int kCullWaveGroups = 16;
+constexpr int kCullBlockGroups = kCullWaveGroups * kWaves;   // 64
+
+template <int PPL>
+__global__ __launch_bounds__(kBlock) void cull_groups(const GroupBound* __restrict__ gb, int ngroups64, int ngroups,
+                                                        const CullRec* __restrict__ culls, int nv, float z_near,
+                                                        uint64_t* __restrict__ mask, uint32_t* __restrict__ counts,
+                                                        uint32_t* __restrict__ aux,
+                                                        unsigned long long* __restrict__ evaluated)
+{
+    __shared__ GroupBound sb[kCullBlockGroups];
+    __shared__ uint32_t hist[kOrderBuckets];
+    // the class counts aux[0, kOrderBuckets) are cleared before this kernel
+    // (by group_bounds, then by each view loop); the cursors and the pair
+    // counters are used only by the kernels after it
+    if (blockIdx.x == 0) {
+        if (threadIdx.x < kOrderBuckets) aux[kOrderBuckets + threadIdx.x] = 0u;
+        if (evaluated && threadIdx.x < kEvalSlots) evaluated[threadIdx.x] = 0ull;
+    }
+    const int gblock = blockIdx.x * kCullBlockGroups;
+    if (threadIdx.x < kCullBlockGroups && gblock + (int)threadIdx.x < ngroups)
+        sb[threadIdx.x] = loop_group_bound<PPL>(gb, ngroups64, gblock + threadIdx.x);
+    if (threadIdx.x < kOrderBuckets) hist[threadIdx.x] = 0u;
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int first = wave * kCullWaveGroups;   // within the block
+    const int nk = min(kCullWaveGroups, ngroups - gblock - first);   // groups of this wave (may be <= 0)
+    const int nwords = (nv + 63) / 64;
+    uint32_t cnt = 0;   // lane k < nk: views of group gblock + first + k
+    for (int b = 0; b < nwords; ++b) {
+        const int v = b * 64 + lane;
+        CullRec q = {};
+        if (v < nv) q = culls[v];
+        for (int k = 0; k < nk; ++k) {
+            const GroupBound g = sb[first + k];
+            const float ca = fabsf(g.c[0]) + fabsf(g.c[1]) + fabsf(g.c[2]);
+            // a non-finite bound (non-finite input) disables culling for the group
+            const bool no_cull = !(g.rm < INFINITY) || !(g.sg < INFINITY) || !(ca < INFINITY);
+            const bool vis = (v < nv) & (no_cull | cull_pass(q, g.c[0], g.c[1], g.c[2], g.h[0], g.h[1], g.h[2], g.rm,
+                                                             g.sg, ca, z_near));
+            const uint64_t m = __ballot(vis);
+            if (lane == 0) mask[(size_t)(gblock + first + k) * nwords + b] = m;
+            if (lane == k) cnt += (uint32_t)__popcll(m);
+        }
+    }
+    if (lane < nk) {
+        counts[gblock + first + lane] = cnt;
+        atomicAdd(&hist[work_class(cnt, nv)], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x < kOrderBuckets && hist[threadIdx.x]) atomicAdd(&aux[threadIdx.x], hist[threadIdx.x]);
+}
+
+// Orders the view-loop groups by work class (most views first) so that the
+// longest groups start early and none is left running alone at the end.
+// Within a class the order is arbitrary: each group's result does not
+// depend on when it runs.
+__global__ __launch_bounds__(kBlock) void place_groups(const uint32_t* __restrict__ counts, int ngroups, int nv,
+                                                         uint32_t* __restrict__ aux, int32_t* __restrict__ order)
+{
+    __shared__ uint32_t base[kOrderBuckets], cls[kOrderBuckets], off[kOrderBuckets];
+    if (threadIdx.x < kOrderBuckets) {
+        uint32_t s = 0;
+        for (int c = 0; c < (int)threadIdx.x; ++c) s += aux[c];
+        base[threadIdx.x] = s;
+        cls[threadIdx.x] = 0u;
+    }
+    __syncthreads();
+    const int G = blockIdx.x * kBlock + threadIdx.x;
+    int c = 0;
+    uint32_t rank = 0;
+    if (G < ngroups) {
+        c = work_class(counts[G], nv);
+        rank = atomicAdd(&cls[c], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x < kOrderBuckets && cls[threadIdx.x])
+        off[threadIdx.x] = atomicAdd(&aux[kOrderBuckets + threadIdx.x], cls[threadIdx.x]);
+    __syncthreads();
+    const uint32_t pos = base[c] + off[c] + rank;   // < ngroups: the classes partition the groups
+    if (G < ngroups && pos < (uint32_t)ngroups) order[pos] = G;
+}
+
+// The view loop: wave w takes group order[w] (PPL kGroup-record groups;
+// lane l holds records l, l + 64, ... of it) and evaluates every view its
+// mask keeps, in increasing view order, for all its records.
 template <int PROJ, int PPL>
 __global__ __launch_bounds__(kBlock) void score_binned(const PrimRec* __restrict__ recs, int n,
                                                          const CamRec* __restrict__ cams,
-                                                         const CullRec* __restrict__ culls, int nv, float eta,
-                                                         float z_near, float* __restrict__ out,
-                                                         unsigned long long* __restrict__ evaluated)
+                                                         const uint64_t* __restrict__ mask,
+                                                         const int32_t* __restrict__ order, int ngroups, int nv,
+                                                         float eta, float z_near, float* __restrict__ out,
+                                                         unsigned long long* __restrict__ evaluated,
+                                                         uint32_t* __restrict__ aux)
 {
     const int lane = threadIdx.x & 63;
-    const int g0 = (blockIdx.x * kBlock + (int)threadIdx.x - lane) * PPL;   // first record of the wave's group
+    // wave-uniform values (readfirstlane tells the compiler so: the mask
+    // words then come in through scalar loads and the loop over their bits
+    // runs on the scalar unit)
+    const int w = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * kBlock + threadIdx.x) >> 6);
+    const bool active = w < ngroups;   // waves past the last group still help load the camera table
+    // (place_groups has read the class counts: clear them for the next view loop)
+    if (blockIdx.x == 0 && threadIdx.x < kOrderBuckets) aux[threadIdx.x] = 0u;
+    const int G = active ? min(max(__builtin_amdgcn_readfirstlane(order[w]), 0), ngroups - 1) : 0;
+    const int g0 = G * kGroup * PPL;
     Prim p[PPL];
     float pre[PPL];
     int idx[PPL];
-    float smax = 0.0f;
 #pragma unroll
     for (int k = 0; k < PPL; ++k) {
         const int j = g0 + k * 64 + lane;
-        const PrimRec r = recs[min(j, n - 1)];   // lanes past the end repeat the last record
+        const int jj = min(j, n - 1);   // lanes past the end repeat the last record
+        const PrimRec r = recs[jj];
         p[k].mx = r.mu[0]; p[k].my = r.mu[1]; p[k].mz = r.mu[2];
         p[k].L00 = r.L[0]; p[k].L01 = r.L[1]; p[k].L02 = r.L[2];
         p[k].L10 = r.L[3]; p[k].L11 = r.L[4]; p[k].L12 = r.L[5];
         p[k].L20 = r.L[6]; p[k].L21 = r.L[7]; p[k].L22 = r.L[8];
         p[k].S = 0.0f;
         pre[k] = r.pre;
-        idx[k] = j < n ? r.idx : -1;
-        smax = fmaxf(smax, r.smax);
+        idx[k] = (active && j < n) ? r.idx : -1;
     }
-    // bounding sphere of the group's centres and its largest scale
-    float lo[3] = {p[0].mx, p[0].my, p[0].mz}, hi[3] = {p[0].mx, p[0].my, p[0].mz};
-#pragma unroll
-    for (int k = 1; k < PPL; ++k) {
-        lo[0] = fminf(lo[0], p[k].mx); hi[0] = fmaxf(hi[0], p[k].mx);
-        lo[1] = fminf(lo[1], p[k].my); hi[1] = fmaxf(hi[1], p[k].my);
-        lo[2] = fminf(lo[2], p[k].mz); hi[2] = fmaxf(hi[2], p[k].mz);
-    }
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        lo[a] = wave_min(lo[a]);
-        hi[a] = wave_max(hi[a]);
-    }
-    const float cx = 0.5f * (lo[0] + hi[0]);
-    const float cy = 0.5f * (lo[1] + hi[1]);
-    const float cz = 0.5f * (lo[2] + hi[2]);
-    float d2 = 0.0f;
-#pragma unroll
-    for (int k = 0; k < PPL; ++k) {
-        const float dx = p[k].mx - cx, dy = p[k].my - cy, dz = p[k].mz - cz;
-        d2 = fmaxf(d2, dx * dx + dy * dy + dz * dz);
-    }
-    const float ca = fabsf(cx) + fabsf(cy) + fabsf(cz);
-    const float abs_m = 1e-4f * (ca + 1.0f);
-    const float rm = sqrtf(wave_max(d2)) * kCullMargin + abs_m;
-    const float hx = 0.5f * (hi[0] - lo[0]) * kCullMargin + abs_m;
-    const float hy = 0.5f * (hi[1] - lo[1]) * kCullMargin + abs_m;
-    const float hz = 0.5f * (hi[2] - lo[2]) * kCullMargin + abs_m;
-    const float sg = wave_max(smax);
-    // a non-finite bound (non-finite input) disables culling for this group
-    const bool no_cull = !(rm < INFINITY) || !(sg < INFINITY) || !(ca < INFINITY);
+    const int nwords = (nv + 63) / 64;
+    const uint64_t* gm = mask + (size_t)G * nwords;
     // the evaluation constants of up to kViewChunk views, loaded into LDS by
     // the whole block, so that every camera operand of the pair arithmetic
     // is a vector register (an instruction may read only one scalar register)
@@ -595,10 +804,7 @@ __global__ __launch_bounds__(kBlock) void score_binned(const PrimRec* __restrict
             table[t] = reinterpret_cast<const float4*>(cams + c0 + t / kStageVec)[t % kStageVec];
         __syncthreads();
         for (int v0 = c0; v0 < c0 + cn; v0 += 64) {
-            const int v = v0 + lane;
-            bool vis = false;
-            if (v < nv) vis = no_cull || cull_pass(culls[v], cx, cy, cz, hx, hy, hz, rm, sg, ca, z_near);
-            uint64_t m = __ballot(vis);
+            uint64_t m = active ? gm[v0 / 64] : 0ull;
             n_eval += (uint32_t)__popcll(m);
             while (m != 0ull) {
                 const int b = __builtin_ctzll(m);
@@ -613,16 +819,11 @@ __global__ __launch_bounds__(kBlock) void score_binned(const PrimRec* __restrict
 #pragma unroll
     for (int k = 0; k < PPL; ++k)
         if (idx[k] >= 0) out[idx[k]] = pre[k] * p[k].S / (float)nv;
-    if (evaluated && lane == 0) {
-        const int valid = max(0, min(64 * PPL, n - g0));   // records of this group
-        const int slot = (g0 / (64 * PPL)) % kEvalSlots;   // spread: one address would serialise the waves
+    if (evaluated && active && lane == 0) {
+        const int valid = max(0, min(kGroup * PPL, n - g0));   // records of this group
+        const int slot = G % kEvalSlots;   // spread: one address would serialise the waves
         atomicAdd(evaluated + slot, (unsigned long long)n_eval * (unsigned long long)valid);
     }
-}
-
-__global__ void counter_reset(unsigned long long* c)
-{
-    if (threadIdx.x < kEvalSlots) c[threadIdx.x] = 0ull;
 }
 
 __global__ void counter_store(const unsigned long long* c, int64_t* out, int64_t direct_pairs)
@@ -645,6 +846,9 @@ void prepare_mode(const void* planes, int64_t stride, int n, const refine_params
                        ws.dest);
     hipLaunchKernelGGL((bin_scatter<PROJ, ST>), grid, dim3(kBlock), 0, stream, planes, stride, n, d_stats, vis, ws.dest,
                        ws.recs);
+    const int ng = (int)num_groups(n, kGroup);
+    hipLaunchKernelGGL(group_bounds, dim3((unsigned)num_groups(ng, kBlock / kBoundLanes)), dim3(kBlock), 0, stream,
+                       ws.recs, n, ws.gbound, ng, ws.gaux);
 }
 
 template <int PROJ, int ST>
@@ -657,13 +861,25 @@ void views_mode(const void* planes, int64_t stride, int n, const refine_params& 
     const dim3 grid((unsigned)((n + kBlock - 1) / kBlock));
     if (binned) {
         const int ppl = prm.records_per_lane > 0 ? prm.records_per_lane : kDefaultPPL;
-        const unsigned blocks = (unsigned)((n + kBlock * ppl - 1) / (kBlock * ppl));
+        const int ng64 = (int)num_groups(n, kGroup);
+        const int ng = (int)num_groups(n, kGroup * ppl);
+        const unsigned gblocks = (unsigned)num_groups(ng, kBlock);
+        const unsigned loop_blocks = (unsigned)num_groups(ng, kWaves);
+        uint32_t* const counts = ws.gcount;
+        const unsigned cblocks = (unsigned)num_groups(ng, kCullBlockGroups);
         if (ppl == 2)
-            hipLaunchKernelGGL((score_binned<PROJ, 2>), dim3(blocks), dim3(kBlock), 0, stream, ws.recs, n, ws.cams,
-                               ws.culls, nv, eta, zn, d_scores, evaluated);
+            hipLaunchKernelGGL(cull_groups<2>, dim3(cblocks), dim3(kBlock), 0, stream, ws.gbound, ng64, ng, ws.culls,
+                               nv, zn, ws.gmask, counts, ws.gaux, evaluated);
         else
-            hipLaunchKernelGGL((score_binned<PROJ, 1>), dim3(blocks), dim3(kBlock), 0, stream, ws.recs, n, ws.cams,
-                               ws.culls, nv, eta, zn, d_scores, evaluated);
+            hipLaunchKernelGGL(cull_groups<1>, dim3(cblocks), dim3(kBlock), 0, stream, ws.gbound, ng64, ng, ws.culls,
+                               nv, zn, ws.gmask, counts, ws.gaux, evaluated);
+        hipLaunchKernelGGL(place_groups, dim3(gblocks), dim3(kBlock), 0, stream, counts, ng, nv, ws.gaux, ws.gorder);
+        if (ppl == 2)
+            hipLaunchKernelGGL((score_binned<PROJ, 2>), dim3(loop_blocks), dim3(kBlock), 0, stream, ws.recs, n,
+                               ws.cams, ws.gmask, ws.gorder, ng, nv, eta, zn, d_scores, evaluated, ws.gaux);
+        else
+            hipLaunchKernelGGL((score_binned<PROJ, 1>), dim3(loop_blocks), dim3(kBlock), 0, stream, ws.recs, n,
+                               ws.cams, ws.gmask, ws.gorder, ng, nv, eta, zn, d_scores, evaluated, ws.gaux);
     } else {
         hipLaunchKernelGGL((score_direct<PROJ, ST>), grid, dim3(kBlock), 0, stream, planes, stride, n, ws.cams, nv,
                            d_stats, eta, zn, vis, d_scores);
@@ -750,7 +966,8 @@ hipError_t launch_score_views(const void* planes, int st, int64_t stride, int64_
     const int nv = views_of(prm, n_views);
     const bool binned = binned_path(prm, n);
     unsigned long long* counter = (d_evaluated && binned) ? ws.evaluated : nullptr;
-    if (counter) hipLaunchKernelGGL(counter_reset, dim3(1), dim3(kEvalSlots), 0, stream, counter);
+    if (binned && n == 0 && counter)   // the view loop, which clears the pair counters, does not run
+        hipLaunchKernelGGL(views_init, dim3(1), dim3(kEvalSlots), 0, stream, counter);
     if (n > 0)
         dispatch_mode(prm.proj_mode, st, [&](auto proj_c, auto st_c) {
             views_mode<decltype(proj_c)::value, decltype(st_c)::value>(planes, stride, (int)n, prm, d_stats, d_scores,
