@@ -90,7 +90,7 @@ size_t workspace_layout(int64_t n, int32_t n_views, bool score, void* base, Work
     const size_t o_gbnd = off;  off += score ? align_up(sizeof(GroupBound) * ng) : 0;
     const size_t o_gord = off;  off += score ? align_up(sizeof(int32_t) * ng) : 0;
     const size_t o_gcnt = off;  off += score ? align_up(sizeof(uint32_t) * ng) : 0;
-    const size_t o_gaux = off;  off += score ? align_up(sizeof(uint32_t) * 2 * kOrderBuckets) : 0;
+    const size_t o_gaux = off;  off += score ? align_up(sizeof(uint32_t) * kOrderAuxWords) : 0;
     const size_t o_cams = off;  off += score ? align_up(sizeof(CamRec) * nv) : 0;
     const size_t o_cull = off;  off += score ? align_up(sizeof(CullRec) * nv) : 0;
     const size_t o_gmsk = off;  off += score ? align_up(sizeof(uint64_t) * ng * ((nv + 63) / 64)) : 0;

@@ -101,6 +101,9 @@ static_assert(sizeof(GroupBound) == 32, "group bound size");
 
 constexpr int kGroup = 64;         // records per group: one per lane of a wave
 constexpr int kOrderBuckets = 32;  // work classes of the group order (most views first)
+constexpr int kOrderCopies = 8;    // copies of the class counts (one per block residue: fewer atomics per address)
+// view-loop order state: kOrderBuckets cursors, then kOrderCopies x kOrderBuckets class counts
+constexpr int kOrderAuxWords = kOrderBuckets * (1 + kOrderCopies);
 
 __host__ __device__ inline int64_t num_groups(int64_t n, int per) { return (n + per - 1) / per; }
 
@@ -126,7 +129,7 @@ struct Workspace {
     GroupBound* gbound;      // [num_groups(n, kGroup)]
     int32_t* gorder;         // [num_groups(n, kGroup)] group order of the view loop
     uint32_t* gcount;        // [num_groups(n, kGroup)] views each view-loop group evaluates
-    uint32_t* gaux;          // [2][kOrderBuckets] work-class counts and cursors
+    uint32_t* gaux;          // [kOrderAuxWords] work-class cursors and counts
     uint64_t* gmask;         // [num_groups(n, kGroup)][ceil(n_views / 64)] views each group evaluates
     unsigned long long* evaluated;   // [kEvalSlots] pairs evaluated by the last view loop
 };

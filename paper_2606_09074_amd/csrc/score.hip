@@ -514,7 +514,8 @@ __global__ __launch_bounds__(kBlock) void group_bounds(const PrimRec* __restrict
                                                          GroupBound* __restrict__ gb, int ngroups,
                                                          uint32_t* __restrict__ aux)
 {
-    if (blockIdx.x == 0 && threadIdx.x < kOrderBuckets) aux[threadIdx.x] = 0u;   // for the first view loop
+    // the class counts start at zero for the first view loop
+    if (blockIdx.x == 0 && threadIdx.x < kOrderBuckets * kOrderCopies) aux[kOrderBuckets + threadIdx.x] = 0u;
     const int t = blockIdx.x * kBlock + threadIdx.x;
     const int g = t / kBoundLanes, sl = t % kBoundLanes;
     const bool ok = g < ngroups;   // whole 16-lane segments
@@ -669,23 +670,25 @@ __global__ void views_init(unsigned long long* __restrict__ evaluated)
 // bounds can pass the near plane or one image edge even with the largest
 // footprint any of its primitives can have.  Also counts each group's views
 // into the block's work classes.
-constexpr int kCullWaveGroups = 16;
-constexpr int kCullBlockGroups = kCullWaveGroups * kWaves;   // 64
+constexpr int kCullThreads = 1024;   // 16 waves share the staged culling records
+constexpr int kCullWaveGroups = 4;
+constexpr int kCullBlockGroups = kCullWaveGroups * (kCullThreads / 64);   // 64
 
 template <int PPL>
-__global__ __launch_bounds__(kBlock) void cull_groups(const GroupBound* __restrict__ gb, int ngroups64, int ngroups,
+__global__ __launch_bounds__(kCullThreads) void cull_groups(const GroupBound* __restrict__ gb, int ngroups64, int ngroups,
                                                         const CullRec* __restrict__ culls, int nv, float z_near,
                                                         uint64_t* __restrict__ mask, uint32_t* __restrict__ counts,
                                                         uint32_t* __restrict__ aux,
                                                         unsigned long long* __restrict__ evaluated)
 {
     __shared__ GroupBound sb[kCullBlockGroups];
+    __shared__ CullRec sc[kViewChunk];   // the culling records of up to kViewChunk views (32 KB)
     __shared__ uint32_t hist[kOrderBuckets];
-    // the class counts aux[0, kOrderBuckets) are cleared before this kernel
-    // (by group_bounds, then by each view loop); the cursors and the pair
+    // the class counts are cleared before this kernel (by group_bounds, then
+    // by each view loop); the cursors aux[0, kOrderBuckets) and the pair
     // counters are used only by the kernels after it
     if (blockIdx.x == 0) {
-        if (threadIdx.x < kOrderBuckets) aux[kOrderBuckets + threadIdx.x] = 0u;
+        if (threadIdx.x < kOrderBuckets) aux[threadIdx.x] = 0u;
         if (evaluated && threadIdx.x < kEvalSlots) evaluated[threadIdx.x] = 0ull;
     }
     const int gblock = blockIdx.x * kCullBlockGroups;
@@ -698,10 +701,17 @@ __global__ __launch_bounds__(kBlock) void cull_groups(const GroupBound* __restri
     const int nk = min(kCullWaveGroups, ngroups - gblock - first);   // groups of this wave (may be <= 0)
     const int nwords = (nv + 63) / 64;
     uint32_t cnt = 0;   // lane k < nk: views of group gblock + first + k
-    for (int b = 0; b < nwords; ++b) {
+    for (int c0 = 0; c0 < nv; c0 += kViewChunk) {
+    const int cn = min(kViewChunk, nv - c0);
+    __syncthreads();   // the previous chunk's reads are done
+    constexpr int kRecVec = sizeof(CullRec) / sizeof(float4);
+    for (int t = threadIdx.x; t < cn * kRecVec; t += kCullThreads)
+        reinterpret_cast<float4*>(sc)[t] = reinterpret_cast<const float4*>(culls + c0)[t];
+    __syncthreads();
+    for (int b = c0 / 64; b < (c0 + cn + 63) / 64; ++b) {
         const int v = b * 64 + lane;
         CullRec q = {};
-        if (v < nv) q = culls[v];
+        if (v < nv) q = sc[v - c0];
         for (int k = 0; k < nk; ++k) {
             const GroupBound g = sb[first + k];
             const float ca = fabsf(g.c[0]) + fabsf(g.c[1]) + fabsf(g.c[2]);
@@ -714,12 +724,14 @@ __global__ __launch_bounds__(kBlock) void cull_groups(const GroupBound* __restri
             if (lane == k) cnt += (uint32_t)__popcll(m);
         }
     }
+    }
     if (lane < nk) {
         counts[gblock + first + lane] = cnt;
         atomicAdd(&hist[work_class(cnt, nv)], 1u);
     }
     __syncthreads();
-    if (threadIdx.x < kOrderBuckets && hist[threadIdx.x]) atomicAdd(&aux[threadIdx.x], hist[threadIdx.x]);
+    if (threadIdx.x < kOrderBuckets && hist[threadIdx.x])
+        atomicAdd(&aux[kOrderBuckets * (1 + blockIdx.x % kOrderCopies) + threadIdx.x], hist[threadIdx.x]);
 }
 
 // Orders the view-loop groups by work class (most views first) so that the
@@ -729,12 +741,18 @@ __global__ __launch_bounds__(kBlock) void cull_groups(const GroupBound* __restri
 __global__ __launch_bounds__(kBlock) void place_groups(const uint32_t* __restrict__ counts, int ngroups, int nv,
                                                          uint32_t* __restrict__ aux, int32_t* __restrict__ order)
 {
-    __shared__ uint32_t base[kOrderBuckets], cls[kOrderBuckets], off[kOrderBuckets];
+    __shared__ uint32_t tot[kOrderBuckets], base[kOrderBuckets], cls[kOrderBuckets], off[kOrderBuckets];
+    if (threadIdx.x < kOrderBuckets) {
+        uint32_t t = 0;
+        for (int k = 0; k < kOrderCopies; ++k) t += aux[kOrderBuckets * (1 + k) + threadIdx.x];
+        tot[threadIdx.x] = t;
+        cls[threadIdx.x] = 0u;
+    }
+    __syncthreads();
     if (threadIdx.x < kOrderBuckets) {
         uint32_t s = 0;
-        for (int c = 0; c < (int)threadIdx.x; ++c) s += aux[c];
+        for (int c = 0; c < (int)threadIdx.x; ++c) s += tot[c];
         base[threadIdx.x] = s;
-        cls[threadIdx.x] = 0u;
     }
     __syncthreads();
     const int G = blockIdx.x * kBlock + threadIdx.x;
@@ -746,7 +764,7 @@ __global__ __launch_bounds__(kBlock) void place_groups(const uint32_t* __restric
     }
     __syncthreads();
     if (threadIdx.x < kOrderBuckets && cls[threadIdx.x])
-        off[threadIdx.x] = atomicAdd(&aux[kOrderBuckets + threadIdx.x], cls[threadIdx.x]);
+        off[threadIdx.x] = atomicAdd(&aux[threadIdx.x], cls[threadIdx.x]);
     __syncthreads();
     const uint32_t pos = base[c] + off[c] + rank;   // < ngroups: the classes partition the groups
     if (G < ngroups && pos < (uint32_t)ngroups) order[pos] = G;
@@ -771,7 +789,7 @@ __global__ __launch_bounds__(kBlock) void score_binned(const PrimRec* __restrict
     const int w = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * kBlock + threadIdx.x) >> 6);
     const bool active = w < ngroups;   // waves past the last group still help load the camera table
     // (place_groups has read the class counts: clear them for the next view loop)
-    if (blockIdx.x == 0 && threadIdx.x < kOrderBuckets) aux[threadIdx.x] = 0u;
+    if (blockIdx.x == 0 && threadIdx.x < kOrderBuckets * kOrderCopies) aux[kOrderBuckets + threadIdx.x] = 0u;
     const int G = active ? min(max(__builtin_amdgcn_readfirstlane(order[w]), 0), ngroups - 1) : 0;
     const int g0 = G * kGroup * PPL;
     Prim p[PPL];
@@ -868,10 +886,10 @@ void views_mode(const void* planes, int64_t stride, int n, const refine_params& 
         uint32_t* const counts = ws.gcount;
         const unsigned cblocks = (unsigned)num_groups(ng, kCullBlockGroups);
         if (ppl == 2)
-            hipLaunchKernelGGL(cull_groups<2>, dim3(cblocks), dim3(kBlock), 0, stream, ws.gbound, ng64, ng, ws.culls,
+            hipLaunchKernelGGL(cull_groups<2>, dim3(cblocks), dim3(kCullThreads), 0, stream, ws.gbound, ng64, ng, ws.culls,
                                nv, zn, ws.gmask, counts, ws.gaux, evaluated);
         else
-            hipLaunchKernelGGL(cull_groups<1>, dim3(cblocks), dim3(kBlock), 0, stream, ws.gbound, ng64, ng, ws.culls,
+            hipLaunchKernelGGL(cull_groups<1>, dim3(cblocks), dim3(kCullThreads), 0, stream, ws.gbound, ng64, ng, ws.culls,
                                nv, zn, ws.gmask, counts, ws.gaux, evaluated);
         hipLaunchKernelGGL(place_groups, dim3(gblocks), dim3(kBlock), 0, stream, counts, ng, nv, ws.gaux, ws.gorder);
         if (ppl == 2)
