@@ -68,7 +68,7 @@ namespace {
 constexpr float kShC0 = 0.28209479177387814f;
 constexpr float kCullMargin = 1.01f;
 constexpr int64_t kBinnedMinPrims = 65536;
-constexpr int kDefaultPPL = 1;   // binned records per lane unless the caller picks
+constexpr int kDefaultPPL = 2;   // binned records per lane unless the caller picks (2: half the culling tests)
 
 // The records of view slot j (cull may be null: no culling records).
 __device__ __forceinline__ void camera_prep_body(const float* __restrict__ cams, int n_views, int nv, float clamp_k,
