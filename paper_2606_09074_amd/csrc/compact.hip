@@ -27,12 +27,12 @@ __device__ __forceinline__ void compact_count_body(const uint8_t* __restrict__ k
                                                           uint32_t* __restrict__ tile_cnt, int blk)
 {
     const int base = blk * kTile;
+    uint8_t f[kItems];   // all flags loaded before any is counted
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) f[k] = keep[min(base + k * kBlock + (int)threadIdx.x, n - 1)];
     uint32_t c = 0;
-#pragma unroll 4
-    for (int k = 0; k < kItems; ++k) {
-        const int i = base + k * kBlock + (int)threadIdx.x;
-        if (i < n && keep[i]) ++c;
-    }
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) c += (base + k * kBlock + (int)threadIdx.x < n && f[k]) ? 1u : 0u;
     c = wave_sum_u32(c);
     __shared__ uint32_t red[kWaves];
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;

@@ -339,13 +339,23 @@ __device__ inline uint32_t cell_of(float x, float y, float z, const refine_stats
 // cell's range holds copy 0's primitives, then copy 1's, and so on.
 constexpr int kCellsPerThread = kCells / kBlock;   // 16
 
-// Morton cell of primitive i's centre.
+// Cells of this thread's kItems primitives of the tile: every centre is
+// loaded before any is quantised (lanes past the end load primitive n - 1;
+// the callers skip them).
 template <int ST>
-__device__ inline uint32_t cell_of_prim(const void* __restrict__ planes, int64_t stride, int i,
-                                        const refine_stats_t* __restrict__ st)
+__device__ inline void tile_cells(const void* __restrict__ planes, int64_t stride, int n, int base,
+                                  const refine_stats_t* __restrict__ st, uint32_t (&cell)[kItems])
 {
-    return cell_of(load_plane<ST>(planes, stride, 0, i), load_plane<ST>(planes, stride, 1, i),
-                   load_plane<ST>(planes, stride, 2, i), st);
+    float x[kItems], y[kItems], z[kItems];
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        const int i = min(base + k * kBlock + (int)threadIdx.x, n - 1);
+        x[k] = load_plane<ST>(planes, stride, 0, i);
+        y[k] = load_plane<ST>(planes, stride, 1, i);
+        z[k] = load_plane<ST>(planes, stride, 2, i);
+    }
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) cell[k] = cell_of(x[k], y[k], z[k], st);
 }
 
 // Cell histogram of the tile's primitives.
@@ -358,11 +368,11 @@ __global__ __launch_bounds__(kBlock) void bin_hist(const void* __restrict__ plan
     for (int c = threadIdx.x; c < kCells; c += kBlock) h[c] = 0u;
     __syncthreads();
     const int base = blockIdx.x * kTile;
-#pragma unroll 4
-    for (int k = 0; k < kItems; ++k) {
-        const int i = base + k * kBlock + (int)threadIdx.x;
-        if (i < n) atomicAdd(&h[cell_of_prim<ST>(planes, stride, i, st)], 1u);
-    }
+    uint32_t cell[kItems];
+    tile_cells<ST>(planes, stride, n, base, st, cell);
+#pragma unroll
+    for (int k = 0; k < kItems; ++k)
+        if (base + k * kBlock + (int)threadIdx.x < n) atomicAdd(&h[cell[k]], 1u);
     __syncthreads();
     const int copy = blockIdx.x % kBinCopies;
 #pragma unroll
@@ -423,15 +433,11 @@ __global__ __launch_bounds__(kBlock) void bin_rank(const void* __restrict__ plan
     __syncthreads();
     const int base = blockIdx.x * kTile;
     uint32_t cell[kItems], rank[kItems];
+    tile_cells<ST>(planes, stride, n, base, st, cell);
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
-        const int i = base + k * kBlock + (int)threadIdx.x;
-        cell[k] = 0u;
         rank[k] = 0u;
-        if (i < n) {
-            cell[k] = cell_of_prim<ST>(planes, stride, i, st);
-            rank[k] = atomicAdd(&h[cell[k]], 1u);
-        }
+        if (base + k * kBlock + (int)threadIdx.x < n) rank[k] = atomicAdd(&h[cell[k]], 1u);
     }
     __syncthreads();
     // all reservations of this thread are issued before any result is used

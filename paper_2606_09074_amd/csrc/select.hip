@@ -173,12 +173,13 @@ __device__ __forceinline__ void select_count_body(const float* __restrict__ scor
 {
     const uint32_t T = st->threshold;
     const int base = blk * kTile;
+    float v[kItems];   // all keys loaded before any is compared
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) v[k] = scores[min(base + k * kBlock + (int)threadIdx.x, n - 1)];
     uint32_t c = 0;
-#pragma unroll 4
-    for (int k = 0; k < kItems; ++k) {
-        const int i = base + k * kBlock + (int)threadIdx.x;
-        if (i < n && float_key(scores[i]) == T) ++c;
-    }
+#pragma unroll
+    for (int k = 0; k < kItems; ++k)
+        c += (base + k * kBlock + (int)threadIdx.x < n && float_key(v[k]) == T) ? 1u : 0u;
     c = wave_sum_u32(c);
     __shared__ uint32_t red[kWaves];
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;

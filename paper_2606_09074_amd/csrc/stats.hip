@@ -123,14 +123,21 @@ __device__ __forceinline__ void stats_partial_body(const void* __restrict__ plan
 {
     const int base = tile * kTile;
     Acc a;
-#pragma unroll 4
-    for (int k = 0; k < kItems; ++k) {
-        const int i = base + k * kBlock + (int)threadIdx.x;
-        if (i >= n) break;
-        float v[kScorePlanes];
+    // kBatch items' planes are loaded before any is used (14 kBatch loads in
+    // flight per lane); lanes past the end load primitive n - 1 and skip it
+    constexpr int kBatch = 4;
+    for (int k0 = 0; k0 < kItems; k0 += kBatch) {
+        if (base + k0 * kBlock >= n) break;   // uniform
+        float v[kBatch][kScorePlanes];
 #pragma unroll
-        for (int p = 0; p < kScorePlanes; ++p) v[p] = load_plane<ST>(planes, stride, p, i);
-        a.add(v, eta);
+        for (int k = 0; k < kBatch; ++k) {
+            const int i = min(base + (k0 + k) * kBlock + (int)threadIdx.x, n - 1);
+#pragma unroll
+            for (int p = 0; p < kScorePlanes; ++p) v[k][p] = load_plane<ST>(planes, stride, p, i);
+        }
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k)
+            if (base + (k0 + k) * kBlock + (int)threadIdx.x < n) a.add(v[k], eta);
     }
     reduce_and_store(a, tile, part);
 }

@@ -295,6 +295,22 @@ def test_binned_and_direct_paths_bit_identical(name, n, mode):
     log(f"[paths {name} n={sub.shape[1]} {mode}] identical; nonzero {int((d['scores'] > 0).sum())}")
 
 
+@pytest.mark.parametrize("rec", [1, 2])
+@pytest.mark.parametrize("n,v", [(5, 3), (777, 1), (9000, 65), (9000, 640)])
+def test_binned_view_masks_and_chunks(n, v, rec):
+    """The binned view phase at its edges: fewer primitives than one group,
+    a single view, a second mask word holding one view, and more views than
+    one LDS camera chunk (several mask words and chunks per group)."""
+    planes, cams, _ = workload("small")
+    sub = np.ascontiguousarray(planes[:, :n])
+    rig = np.ascontiguousarray(np.concatenate([cams] * (v // cams.shape[0] + 1))[:v])
+    d, b = _paths(sub, rig, records_per_lane=rec)
+    np.testing.assert_array_equal(b["scores"].view(np.uint32), d["scores"].view(np.uint32))
+    if n >= 777:
+        F, lam, D, lo, hi = oracle_all(sub, rig)
+        check_scores(b["scores"], D, lo, hi, f"binned n={n} V={v} rec={rec}")
+
+
 def test_binned_path_with_degenerate_and_nonfinite_inputs():
     planes, cams, _ = workload("small")
     sub = np.ascontiguousarray(planes[:, :20000])
