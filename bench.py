@@ -94,6 +94,8 @@ def main() -> int:
                     help="refine_score scheduling (results are bit-identical across paths)")
     ap.add_argument("--records-per-lane", type=int, default=0, choices=[0, 1, 2],
                     help="binned records each lane of the view loop holds (0: the library's default)")
+    ap.add_argument("--views-per-iteration", type=int, default=0, choices=[0, 1, 2],
+                    help="views the binned view loop evaluates per iteration (0: the library's default)")
     ap.add_argument("--storage", default="f32", choices=["f32", "bf16-f16"],
                     help="scene storage: FP32 planes, or BF16 geometry/opacity + FP16 SH (arithmetic is FP32 either way)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -148,6 +150,7 @@ def main() -> int:
     params = _lib.default_params()
     params.score_path = {"auto": _lib.PATH_AUTO, "direct": _lib.PATH_DIRECT, "binned": _lib.PATH_BINNED}[args.score_path]
     params.records_per_lane = args.records_per_lane
+    params.views_per_iteration = args.views_per_iteration
     ws = api.workspace(n, V, dev)
     st = torch.empty(_lib.STATS_BYTES, dtype=torch.uint8, device=dev)
     scores = torch.empty(n, dtype=torch.float32, device=dev)
@@ -256,6 +259,7 @@ def main() -> int:
             "data": "synthetic",
             "config": {"workload": spec.name, "n": n, "views": V, "ratio": ratio, "storage": args.storage,
                        "step": "stats+score+select+compact", "score_path": args.score_path, "records_per_lane": args.records_per_lane,
+                       "views_per_iteration": args.views_per_iteration,
                        "ms_per_prune": round(ms_per_step, 4)},
             "phases_ms": {k: round(v, 4) for k, v in avg.items()},
             "roofline": roofline, "cpu_baseline": cpu, "serving": serving}

@@ -110,6 +110,11 @@ typedef struct {
  *           binned path only, again never a change of results: 0 = the
  *           library's choice, 1 or 2 primitives per lane (a wave's group is
  *           64 or 128 spatially close primitives sharing one view list)
+ *  views_per_iteration
+ *           binned path only, never a change of results: 0 = the library's
+ *           choice, 1 or 2 views evaluated per iteration of the view loop (two
+ *           independent evaluations interleaved; each primitive's sum still
+ *           adds the views in increasing order)
  */
 typedef struct {
     double eta;
@@ -124,6 +129,7 @@ typedef struct {
     int32_t n_sub_views;
     int32_t score_path;
     int32_t records_per_lane;
+    int32_t views_per_iteration;
 } refine_params;
 
 typedef enum { REFINE_PATH_AUTO = 0, REFINE_PATH_DIRECT = 1, REFINE_PATH_BINNED = 2 } refine_score_path;

@@ -39,7 +39,8 @@ class Params(ctypes.Structure):
                 ("e_col", ctypes.c_double), ("e_opa", ctypes.c_double), ("e_lngem", ctypes.c_double),
                 ("proj_mode", ctypes.c_int32), ("vis_mode", ctypes.c_int32),
                 ("equal_lambda", ctypes.c_int32), ("n_sub_views", ctypes.c_int32),
-                ("score_path", ctypes.c_int32), ("records_per_lane", ctypes.c_int32)]
+                ("score_path", ctypes.c_int32), ("records_per_lane", ctypes.c_int32),
+                ("views_per_iteration", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):

@@ -15,6 +15,11 @@ constexpr size_t kAlign = 256;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
+// the Python binding mirrors these layouts (tests/test_abi.py checks the same sizes)
+static_assert(sizeof(refine_scene) == 32, "refine_scene layout");
+static_assert(sizeof(refine_params) == 80, "refine_params layout");
+static_assert(sizeof(refine_stats_t) == 96, "refine_stats_t layout");
+
 bool finite(double x) { return std::isfinite(x); }
 
 bool known_dtype(int32_t d) { return d == REFINE_F32 || d == REFINE_BF16 || d == REFINE_F16; }
@@ -51,6 +56,7 @@ refine_status check_params(const refine_params* p)
     if (p->n_sub_views < 0) return REFINE_E_INVALID;
     if (p->score_path < REFINE_PATH_AUTO || p->score_path > REFINE_PATH_BINNED) return REFINE_E_INVALID;
     if (p->records_per_lane < 0 || p->records_per_lane > 2) return REFINE_E_INVALID;
+    if (p->views_per_iteration < 0 || p->views_per_iteration > 2) return REFINE_E_INVALID;
     return REFINE_OK;
 }
 

@@ -69,6 +69,7 @@ constexpr float kShC0 = 0.28209479177387814f;
 constexpr float kCullMargin = 1.01f;
 constexpr int64_t kBinnedMinPrims = 65536;
 constexpr int kDefaultPPL = 2;   // binned records per lane unless the caller picks (2: half the culling tests)
+constexpr int kDefaultVPI = 1;   // views per iteration of the binned view loop unless the caller picks
 
 // The records of view slot j (cull may be null: no culling records).
 __device__ __forceinline__ void camera_prep_body(const float* __restrict__ cams, int n_views, int nv, float clamp_k,
@@ -778,8 +779,10 @@ __global__ __launch_bounds__(kBlock) void place_groups(const uint32_t* __restric
 
 // The view loop: wave w takes group order[w] (PPL kGroup-record groups;
 // lane l holds records l, l + 64, ... of it) and evaluates every view its
-// mask keeps, in increasing view order, for all its records.
-template <int PROJ, int PPL>
+// mask keeps, in increasing view order, for all its records; VPI = 2 takes
+// two kept views per iteration (two independent evaluation chains to
+// interleave; the sums still add the views in order).
+template <int PROJ, int PPL, int VPI>
 __global__ __launch_bounds__(kBlock) void score_binned(const PrimRec* __restrict__ recs, int n,
                                                          const CamRec* __restrict__ cams,
                                                          const uint64_t* __restrict__ mask,
@@ -835,8 +838,20 @@ __global__ __launch_bounds__(kBlock) void score_binned(const PrimRec* __restrict
                 m &= m - 1ull;
                 CamEval c;
                 load_cam(table + (v0 - c0 + b) * kStageVec, c);
+                if (VPI == 2 && m != 0ull) {
+                    const int b2 = __builtin_ctzll(m);
+                    m &= m - 1ull;
+                    CamEval c2;
+                    load_cam(table + (v0 - c0 + b2) * kStageVec, c2);
 #pragma unroll
-                for (int k = 0; k < PPL; ++k) eval_pair<PROJ>(c, p[k], eta, z_near);
+                    for (int k = 0; k < PPL; ++k) {
+                        eval_pair<PROJ>(c, p[k], eta, z_near);
+                        eval_pair<PROJ>(c2, p[k], eta, z_near);
+                    }
+                } else {
+#pragma unroll
+                    for (int k = 0; k < PPL; ++k) eval_pair<PROJ>(c, p[k], eta, z_near);
+                }
             }
         }
     }
@@ -898,12 +913,15 @@ void views_mode(const void* planes, int64_t stride, int n, const refine_params& 
             hipLaunchKernelGGL(cull_groups<1>, dim3(cblocks), dim3(kCullThreads), 0, stream, ws.gbound, ng64, ng, ws.culls,
                                nv, zn, ws.gmask, counts, ws.gaux, evaluated);
         hipLaunchKernelGGL(place_groups, dim3(gblocks), dim3(kBlock), 0, stream, counts, ng, nv, ws.gaux, ws.gorder);
+        const int vpi = prm.views_per_iteration > 0 ? prm.views_per_iteration : kDefaultVPI;
+        auto loop = [&](auto kernel) {
+            hipLaunchKernelGGL(kernel, dim3(loop_blocks), dim3(kBlock), 0, stream, ws.recs, n, ws.cams, ws.gmask,
+                               ws.gorder, ng, nv, eta, zn, d_scores, evaluated, ws.gaux);
+        };
         if (ppl == 2)
-            hipLaunchKernelGGL((score_binned<PROJ, 2>), dim3(loop_blocks), dim3(kBlock), 0, stream, ws.recs, n,
-                               ws.cams, ws.gmask, ws.gorder, ng, nv, eta, zn, d_scores, evaluated, ws.gaux);
+            vpi == 2 ? loop(score_binned<PROJ, 2, 2>) : loop(score_binned<PROJ, 2, 1>);
         else
-            hipLaunchKernelGGL((score_binned<PROJ, 1>), dim3(loop_blocks), dim3(kBlock), 0, stream, ws.recs, n,
-                               ws.cams, ws.gmask, ws.gorder, ng, nv, eta, zn, d_scores, evaluated, ws.gaux);
+            vpi == 2 ? loop(score_binned<PROJ, 1, 2>) : loop(score_binned<PROJ, 1, 1>);
     } else {
         hipLaunchKernelGGL((score_direct<PROJ, ST>), grid, dim3(kBlock), 0, stream, planes, stride, n, ws.cams, nv,
                            d_stats, eta, zn, vis, d_scores);

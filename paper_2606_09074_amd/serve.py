@@ -117,17 +117,27 @@ def bucket_of(n: int, n_views: int) -> tuple[int, int]:
     return (int(round(math.log2(max(n, 1)))), int(round(math.log2(max(n_views, 1)))))
 
 
-# execution choices of the view loop: (score_path, records_per_lane)
-CANDIDATES = ((1, 0), (2, 1), (2, 2))
+# execution choices of the view loop: (score_path, records_per_lane,
+# views_per_iteration) -- primitives per lane and views per iteration of the
+# binned loop, or the direct loop
+CANDIDATES = ((1, 0, 0), (2, 1, 1), (2, 2, 1), (2, 1, 2), (2, 2, 2))
+
+
+def apply_choice(prm, cand) -> None:
+    """Set a tuner choice (path, records per lane[, views per iteration])
+    on a params struct (choices saved before views per iteration was tuned
+    have two entries)."""
+    prm.score_path, prm.records_per_lane = cand[0], cand[1]
+    prm.views_per_iteration = cand[2] if len(cand) > 2 else 0
 
 
 class Tuner:
     """Per-bucket choice of the view loop's execution (never its results)."""
 
     def __init__(self, table: Optional[dict] = None):
-        self.table: dict[tuple[int, int], tuple[int, int]] = dict(table or {})
+        self.table: dict[tuple[int, int], tuple[int, ...]] = dict(table or {})
 
-    def choice(self, n: int, n_views: int) -> Optional[tuple[int, int]]:
+    def choice(self, n: int, n_views: int) -> Optional[tuple[int, ...]]:
         return self.table.get(bucket_of(n, n_views))
 
     def save(self, path: str) -> None:
@@ -157,9 +167,9 @@ class Tuner:
             st = torch.empty(_lib.STATS_BYTES, dtype=torch.uint8, device=dev)
             scores = torch.empty(n, dtype=torch.float32, device=dev)
             best = None
-            for path, ppl in CANDIDATES:
+            for cand in CANDIDATES:
                 prm = _lib.default_params()
-                prm.score_path, prm.records_per_lane = path, ppl
+                apply_choice(prm, cand)
                 times = []
                 for r in range(reps + 1):
                     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -172,10 +182,11 @@ class Tuner:
                         times.append(e0.elapsed_time(e1))
                 t = float(np.median(times))
                 if best is None or t < best[0]:
-                    best = (t, (path, ppl))
+                    best = (t, cand)
             self.table[(lb_n, lb_v)] = best[1]
             if log:
-                log(f"tuner: bucket n=2^{lb_n} V=2^{lb_v} -> path {best[1][0]} ppl {best[1][1]} ({best[0]:.3f} ms)")
+                log(f"tuner: bucket n=2^{lb_n} V=2^{lb_v} -> path {best[1][0]} ppl {best[1][1]} vpi {best[1][2]} "
+                    f"({best[0]:.3f} ms)")
 
 
 # ------------------------------------------------------------------ server
@@ -313,7 +324,7 @@ class Server:
         if self.tuner is not None and params is None:
             c = self.tuner.choice(n, V)
             if c is not None:
-                prm.score_path, prm.records_per_lane = c
+                apply_choice(prm, c)
         n_keep = n - api.prune_count(n, ratio)
         job = Job(self._next_id, scene, cams, float(ratio), prm,
                   time.perf_counter() if t_arrival is None else t_arrival, n=n, n_keep=n_keep)

@@ -43,7 +43,7 @@ def test_every_declared_function_is_exported(lib):
 def test_struct_sizes_match_header():
     from paper_2606_09074_amd import _lib
     assert ctypes.sizeof(_lib.Scene) == 32
-    assert ctypes.sizeof(_lib.Params) == 72
+    assert ctypes.sizeof(_lib.Params) == 80
     assert ctypes.sizeof(_lib.Stats) == 96
 
 
@@ -55,7 +55,8 @@ def test_version_status_defaults(lib):
     from tests.helpers import CLAMP_K, E_COL, E_LNGEM, E_OPA, ETA, Z_NEAR
     assert (p.eta, p.z_near, p.clamp_k, p.e_col, p.e_opa, p.e_lngem) == (ETA, Z_NEAR, CLAMP_K, E_COL, E_OPA,
                                                                           E_LNGEM)
-    assert (p.proj_mode, p.vis_mode, p.equal_lambda, p.n_sub_views, p.score_path, p.records_per_lane) == (0,) * 6
+    assert (p.proj_mode, p.vis_mode, p.equal_lambda, p.n_sub_views, p.score_path, p.records_per_lane,
+            p.views_per_iteration) == (0,) * 7
 
 
 def test_prune_count(lib):
@@ -118,7 +119,7 @@ def test_stats_validation(lib):
     for field, bad in (("eta", 0.0), ("eta", float("nan")), ("z_near", -1.0), ("clamp_k", 0.0),
                        ("e_col", 0.0), ("e_lngem", float("inf")), ("proj_mode", 3), ("vis_mode", -1),
                        ("equal_lambda", 2), ("n_sub_views", -5), ("score_path", 3), ("records_per_lane", 3),
-                       ("records_per_lane", -1)):
+                       ("records_per_lane", -1), ("views_per_iteration", 3), ("views_per_iteration", -1)):
         q = _lib.default_params()
         setattr(q, field, bad)
         assert call(_scene(), prm=q) == E, field

@@ -284,7 +284,9 @@ def _paths(planes, cams, n=None, **kw):
                                          ("small", None, dict(proj_mode=1)), ("small", None, dict(proj_mode=2)),
                                          ("small", None, dict(vis_mode=1, n_sub_views=6)),
                                          ("medium", 400_000, {}), ("small", 9000, dict(records_per_lane=2)),
-                                         ("medium", 400_000, dict(records_per_lane=2))])
+                                         ("medium", 400_000, dict(records_per_lane=2)),
+                                         ("small", 9000, dict(records_per_lane=1, views_per_iteration=2)),
+                                         ("medium", 400_000, dict(records_per_lane=2, views_per_iteration=2))])
 def test_binned_and_direct_paths_bit_identical(name, n, mode):
     """Culling skips only (group, view) pairs whose every primitive is gated
     out, so the binned path must reproduce the direct path bit for bit."""
@@ -295,18 +297,18 @@ def test_binned_and_direct_paths_bit_identical(name, n, mode):
     log(f"[paths {name} n={sub.shape[1]} {mode}] identical; nonzero {int((d['scores'] > 0).sum())}")
 
 
-@pytest.mark.parametrize("rec", [1, 2])
+@pytest.mark.parametrize("rec,vpi", [(1, 1), (2, 1), (2, 2)])
 @pytest.mark.parametrize("n,v", [(5, 3), (777, 1), (9000, 65), (9000, 640)])
-def test_binned_view_masks_and_chunks(n, v, rec):
+def test_binned_view_masks_and_chunks(n, v, rec, vpi):
     """The binned view phase at its edges: fewer primitives than one group,
     a single view, a second mask word holding one view, and more views than
     one LDS camera chunk (several mask words and chunks per group)."""
     planes, cams, _ = workload("small")
     sub = np.ascontiguousarray(planes[:, :n])
     rig = np.ascontiguousarray(np.concatenate([cams] * (v // cams.shape[0] + 1))[:v])
-    d, b = _paths(sub, rig, records_per_lane=rec)
+    d, b = _paths(sub, rig, records_per_lane=rec, views_per_iteration=vpi)
     np.testing.assert_array_equal(b["scores"].view(np.uint32), d["scores"].view(np.uint32))
-    if n >= 777:
+    if n >= 777 and vpi == 1:
         F, lam, D, lo, hi = oracle_all(sub, rig)
         check_scores(b["scores"], D, lo, hi, f"binned n={n} V={v} rec={rec}")
 
