@@ -422,6 +422,8 @@ refine_status refine_prune_batch(const refine_prune_job* jobs, int32_t n_jobs, c
                         (((size_t)j.scene.stride * es) % 16 == 0) &&
                         (reinterpret_cast<uintptr_t>(j.d_keep) % 4 == 0);
         b.pair_store = (reinterpret_cast<uintptr_t>(j.out.planes) % 4 == 0) && (j.out.stride % 2 == 0);
+        b.vec_stats = (reinterpret_cast<uintptr_t>(j.scene.planes) % 16 == 0) &&
+                      (((size_t)j.scene.stride * es) % 16 == 0);
     }
     if (tiles > INT32_MAX || blocks > INT32_MAX) return REFINE_E_UNSUPPORTED;
     hipStream_t strm = static_cast<hipStream_t>(stream);

@@ -172,6 +172,7 @@ struct BatchJob {
     int32_t block0;          // first 256-primitive block in the batch's block numbering
     int32_t vec_compact;     // 16-byte-load compaction applies
     int32_t pair_store;      // 2-byte output written two elements per store
+    int32_t vec_stats;       // 16-byte-load statistics apply (as in the single-scene call)
 };
 
 // Index of the job whose range [first, next first) holds b (first of job 0 is 0).

@@ -142,6 +142,67 @@ __device__ __forceinline__ void stats_partial_body(const void* __restrict__ plan
     reduce_and_store(a, tile, part);
 }
 
+// stats_partial for 16-byte aligned planes (stride a multiple of 16 bytes):
+// a tile is rows of 16 bytes per lane (4 rows of 1024 FP32 primitives, or 2
+// rows of 2048 2-byte primitives), each plane of a lane's PER consecutive
+// primitives one 16-byte load; the same items, accumulated in the same
+// order per thread as a lane's share of the tile (a different order from
+// stats_partial: the sums agree to FP64 rounding).
+template <int ST>
+__device__ __forceinline__ void stats_partial_vec_body(const void* __restrict__ planes, int64_t stride, int n,
+                                                       float eta, double* __restrict__ part, int tile)
+{
+    constexpr int PER = ST == kStoreF32 ? 4 : 8;        // primitives per 16-byte load
+    constexpr int ROWS = kTile / (PER * kBlock);        // 4 or 2
+    const int base = tile * kTile;
+    Acc a;
+    for (int r = 0; r < ROWS; ++r) {
+        const int i0 = base + r * PER * kBlock + PER * (int)threadIdx.x;
+        if (base + r * PER * kBlock >= n) break;   // uniform
+        if (i0 + PER - 1 < n) {
+            uint4 w[kScorePlanes];
+#pragma unroll
+            for (int p = 0; p < kScorePlanes; ++p) {
+                const char* pl = static_cast<const char*>(planes) + ((int64_t)p * stride + i0) * storage_bytes(ST);
+                w[p] = *reinterpret_cast<const uint4*>(pl);
+            }
+#pragma unroll
+            for (int j = 0; j < PER; ++j) {
+                float v[kScorePlanes];
+#pragma unroll
+                for (int p = 0; p < kScorePlanes; ++p) {
+                    const uint32_t word = j / (PER / 4) == 0 ? w[p].x : j / (PER / 4) == 1 ? w[p].y
+                                        : j / (PER / 4) == 2 ? w[p].z : w[p].w;
+                    if constexpr (ST == kStoreF32) {
+                        v[p] = __uint_as_float(word);
+                    } else {
+                        const uint16_t b = (uint16_t)((j & 1) ? (word >> 16) : (word & 0xFFFFu));
+                        v[p] = p < kGeomPlanes ? __uint_as_float((uint32_t)b << 16)
+                                               : (float)__builtin_bit_cast(_Float16, b);
+                    }
+                }
+                a.add(v, eta);
+            }
+        } else {
+            for (int j = 0; j < PER; ++j) {
+                if (i0 + j >= n) break;
+                float v[kScorePlanes];
+#pragma unroll
+                for (int p = 0; p < kScorePlanes; ++p) v[p] = load_plane<ST>(planes, stride, p, i0 + j);
+                a.add(v, eta);
+            }
+        }
+    }
+    reduce_and_store(a, tile, part);
+}
+
+template <int ST>
+__global__ __launch_bounds__(kBlock) void stats_partial_vec(const void* __restrict__ planes, int64_t stride, int n,
+                                                              float eta, double* __restrict__ part)
+{
+    stats_partial_vec_body<ST>(planes, stride, n, eta, part, blockIdx.x);
+}
+
 template <int ST>
 __global__ __launch_bounds__(kBlock) void stats_partial(const void* __restrict__ planes, int64_t stride,
                                                           int n, float eta, double* __restrict__ part)
@@ -237,8 +298,13 @@ __global__ __launch_bounds__(kBlock) void stats_partial_batch(const BatchJob* __
 {
     const BatchJob& b = jobs[batch_job_of<true>(jobs, nj, blockIdx.x)];
     const int tile = (int)blockIdx.x - b.tile0;
-    if (b.st == kStoreF32)
+    // the same kernel body the single-scene call picks, so the results agree bit for bit
+    if (b.st == kStoreF32 && b.vec_stats)
+        stats_partial_vec_body<kStoreF32>(b.planes, b.stride, b.n, eta, b.stat_part, tile);
+    else if (b.st == kStoreF32)
         stats_partial_body<kStoreF32>(b.planes, b.stride, b.n, eta, b.stat_part, tile);
+    else if (b.vec_stats)
+        stats_partial_vec_body<kStoreBF16F16>(b.planes, b.stride, b.n, eta, b.stat_part, tile);
     else
         stats_partial_body<kStoreBF16F16>(b.planes, b.stride, b.n, eta, b.stat_part, tile);
 }
@@ -265,9 +331,16 @@ hipError_t launch_stats(const void* planes, int st, int64_t stride, int64_t n, c
 {
     const int ntiles = (int)num_tiles(n);
     if (ntiles > 0) {
-        if (st == kStoreF32)
+        const bool vec = reinterpret_cast<uintptr_t>(planes) % 16 == 0 && (stride * storage_bytes(st)) % 16 == 0;
+        if (st == kStoreF32 && vec)
+            hipLaunchKernelGGL(stats_partial_vec<kStoreF32>, dim3(ntiles), dim3(kBlock), 0, stream, planes, stride,
+                               (int)n, (float)prm.eta, ws.stat_part);
+        else if (st == kStoreF32)
             hipLaunchKernelGGL(stats_partial<kStoreF32>, dim3(ntiles), dim3(kBlock), 0, stream, planes, stride,
                                (int)n, (float)prm.eta, ws.stat_part);
+        else if (vec)
+            hipLaunchKernelGGL(stats_partial_vec<kStoreBF16F16>, dim3(ntiles), dim3(kBlock), 0, stream, planes,
+                               stride, (int)n, (float)prm.eta, ws.stat_part);
         else
             hipLaunchKernelGGL(stats_partial<kStoreBF16F16>, dim3(ntiles), dim3(kBlock), 0, stream, planes, stride,
                                (int)n, (float)prm.eta, ws.stat_part);
