@@ -670,10 +670,11 @@ __global__ void views_init(unsigned long long* __restrict__ evaluated)
     if (threadIdx.x < kEvalSlots) evaluated[threadIdx.x] = 0ull;
 }
 
-// The views each view-loop group evaluates, as 64-bit masks: a block takes
-// 64 groups (their bounds staged in LDS), each wave 16 of them; lane l holds
-// the culling record of view 64 b + l in registers and tests it against
-// each group in turn.  A view is dropped only when no point of the group's
+// The views each view-loop group evaluates, as 64-bit masks: a block of 16
+// waves takes 64 groups (their bounds staged in LDS, with the culling
+// records of up to kViewChunk views), each wave 4 of them; lane l holds the
+// culling record of view 64 b + l in registers and tests it against each of
+// the wave's groups in turn.  A view is dropped only when no point of the group's
 // bounds can pass the near plane or one image edge even with the largest
 // footprint any of its primitives can have.  Also counts each group's views
 // into the block's work classes.
