@@ -83,6 +83,8 @@ size_t workspace_layout(int64_t n, int32_t n_views, bool score, void* base, Work
     const size_t o_part = off;  off += align_up(sizeof(double) * kStatSlots * nt);
     const size_t o_cnt = off;   off += align_up(sizeof(uint32_t) * nt);
     const size_t o_toff = off;  off += align_up(sizeof(uint32_t) * nt);
+    const bool rows = num_tiles(n) <= kPrefixTilesMax;
+    const size_t o_rows = off;  off += rows ? align_up(sizeof(uint32_t) * kSelectLastBins * nt) : 0;
     // sections only refine_score uses come after, so the other calls need a
     // prefix only; the camera tables come last, so that no other section's
     // place depends on the number of views (a workspace prepared for one
@@ -107,6 +109,7 @@ size_t workspace_layout(int64_t n, int32_t n_views, bool score, void* base, Work
         ws->stat_part = reinterpret_cast<double*>(b + o_part);
         ws->tile_cnt = reinterpret_cast<uint32_t*>(b + o_cnt);
         ws->tile_off = reinterpret_cast<uint32_t*>(b + o_toff);
+        ws->tile_rows = rows ? reinterpret_cast<uint32_t*>(b + o_rows) : nullptr;
         ws->cams = score ? reinterpret_cast<CamRec*>(b + o_cams) : nullptr;
         ws->culls = score ? reinterpret_cast<CullRec*>(b + o_cull) : nullptr;
         ws->cell_cnt = score ? reinterpret_cast<uint32_t*>(b + o_ccnt) : nullptr;
@@ -132,12 +135,13 @@ namespace {
 constexpr int32_t kMaxBatchJobs = 4096;
 
 // Bytes of one job's workspace slice: selection state and histograms, tile
-// partials and counts, camera records.
+// partials, counts and last-pass rows, camera records.
 size_t batch_job_bytes(int64_t n, int32_t nv)
 {
     const size_t nt = (size_t)num_tiles(n);
     return align_up(sizeof(SelectState)) + align_up(sizeof(uint32_t) * kSelectHistWords) +
-           align_up(sizeof(double) * kStatSlots * nt) + align_up(sizeof(uint32_t) * nt) + align_up(sizeof(CamRec) * nv);
+           align_up(sizeof(double) * kStatSlots * nt) + align_up(sizeof(uint32_t) * nt) +
+           align_up(sizeof(uint32_t) * kSelectLastBins * nt) + align_up(sizeof(CamRec) * nv);
 }
 
 refine_status check_batch_job(const refine_prune_job& j)
@@ -412,6 +416,8 @@ refine_status refine_prune_batch(const refine_prune_job* jobs, int32_t n_jobs, c
         off += align_up(sizeof(double) * kStatSlots * nt);
         b.tile_cnt = reinterpret_cast<uint32_t*>(base + off);
         off += align_up(sizeof(uint32_t) * nt);
+        b.tile_rows = reinterpret_cast<uint32_t*>(base + off);
+        off += align_up(sizeof(uint32_t) * kSelectLastBins * nt);
         b.cam_rec = reinterpret_cast<CamRec*>(base + off);
         off += align_up(sizeof(CamRec) * (size_t)nv);
         b.tile0 = (int32_t)tiles;

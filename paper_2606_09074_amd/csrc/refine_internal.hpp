@@ -31,6 +31,7 @@ constexpr int kHistBits = 11;
 constexpr int kHistBins = 1 << kHistBits;
 constexpr int kHistCopies = 8;    // selection histogram copies: spreads the atomics on crowded bins
 constexpr int kSelectHistWords = 3 * kHistCopies * kHistBins;   // one set of copies per radix pass
+constexpr int kSelectLastBins = 1 << 10;   // digits of the last radix pass (its per-tile rows)
 constexpr int kStatSlots = 8;      // doubles per stats partial
 
 // Prepared camera record (fp32, 128 bytes), built by camera_prep.  Pixel
@@ -119,6 +120,7 @@ struct Workspace {
     double* stat_part;       // [ntiles][kStatSlots]
     uint32_t* tile_cnt;      // [ntiles]
     uint32_t* tile_off;      // [ntiles]
+    uint32_t* tile_rows;     // [ntiles][kSelectLastBins] when ntiles <= kPrefixTilesMax, else null
     // refine_score only:
     CamRec* cams;            // [n_views]
     CullRec* culls;          // [n_views]
@@ -168,6 +170,7 @@ struct BatchJob {
     struct SelectState* sel;
     uint32_t* hist;          // [kSelectHistWords]
     uint32_t* tile_cnt;      // [ntiles]
+    uint32_t* tile_rows;     // [ntiles][kSelectLastBins]
     int32_t tile0;           // first tile in the batch's tile numbering
     int32_t block0;          // first 256-primitive block in the batch's block numbering
     int32_t vec_compact;     // 16-byte-load compaction applies
@@ -332,12 +335,13 @@ __device__ inline uint32_t block_exclusive_scan(const uint32_t* __restrict__ cnt
 // counts of the tiles before it (no separate scan launch).
 constexpr int kPrefixTilesMax = 4096;
 
-// Sum of cnt[0..m) by one block of kBlock threads; every thread gets it.
-__device__ inline uint64_t block_sum_prefix(const uint32_t* __restrict__ cnt, int m)
+// Sum of cnt[0], cnt[stride], ... (m terms) by one block of kBlock threads;
+// every thread gets it.
+__device__ inline uint64_t block_sum_prefix(const uint32_t* __restrict__ cnt, int m, int stride = 1)
 {
     __shared__ uint64_t part[kWaves];
     uint64_t s = 0;
-    for (int t = threadIdx.x; t < m; t += kBlock) s += cnt[t];
+    for (int t = threadIdx.x; t < m; t += kBlock) s += cnt[(size_t)t * stride];
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
     __syncthreads();

@@ -17,8 +17,14 @@
 // the tiles before.  Integer arithmetic throughout, so the mask equals a
 // stable sort by (score, index).
 //
-// Launches: init, 3 x (histogram, find), count, mask -- once per call, or
-// once for all the jobs of a batch (select_*_batch, the same bodies).
+// The last histogram pass also writes each tile's row of last-digit counts
+// (4 KB per tile, from the LDS histogram it builds anyway): once T is known,
+// the count of keys equal to T in tile t is row t at T's last digit, so no
+// separate counting pass over the keys is needed.  (Inputs of more than
+// kPrefixTilesMax tiles count per tile and scan in separate launches.)
+//
+// Launches: init, 3 x (histogram, find), mask -- once per call, or once for
+// all the jobs of a batch (select_*_batch, the same bodies).
 #include "refine_internal.hpp"
 
 namespace refine {
@@ -27,6 +33,7 @@ namespace {
 
 constexpr int kPassShift[3] = {21, 10, 0};
 constexpr int kPassBits[3] = {11, 11, 10};
+static_assert(1 << kPassBits[2] == kSelectLastBins, "last-pass rows hold one counter per digit");
 
 // Clears the histograms of all three passes and sets up the state.
 __global__ void select_init(SelectState* __restrict__ st, uint32_t* __restrict__ hist, int64_t n, int64_t n_prune)
@@ -117,10 +124,12 @@ __global__ __launch_bounds__(kScanThreads) void select_find(SelectState* __restr
 // One tile per block: all 16 keys of a thread are loaded before any is
 // counted, and the crowded bins (many equal exponents, exact zeros) are
 // counted per wave -- the lanes that share the lowest counting lane's bin
-// add with one LDS atomic.
+// add with one LDS atomic.  rows (last pass only, else null): the tile's
+// counts are also stored as its row.
 __device__ __forceinline__ void select_hist_body(const float* __restrict__ scores, int n,
                                                         const SelectState* __restrict__ st, int shift, int bits,
-                                                        uint32_t* __restrict__ hist, int blk)
+                                                        uint32_t* __restrict__ hist, uint32_t* __restrict__ rows,
+                                                        int blk)
 {
     constexpr uint32_t kNoBin = 0xFFFFFFFFu;
     __shared__ uint32_t h[kHistBins];
@@ -157,14 +166,15 @@ __device__ __forceinline__ void select_hist_body(const float* __restrict__ score
     for (int b = threadIdx.x; b < nb; b += kBlock) {
         const uint32_t c = h[b];
         if (c) atomicAdd(&hist[(blk % kHistCopies) * kHistBins + b], c);
+        if (rows) rows[(size_t)blk * kSelectLastBins + b] = c;
     }
 }
 
 __global__ __launch_bounds__(kBlock) void select_hist(const float* __restrict__ scores, int n,
                                                         const SelectState* __restrict__ st, int shift, int bits,
-                                                        uint32_t* __restrict__ hist)
+                                                        uint32_t* __restrict__ hist, uint32_t* __restrict__ rows)
 {
-    select_hist_body(scores, n, st, shift, bits, hist, blockIdx.x);
+    select_hist_body(scores, n, st, shift, bits, hist, rows, blockIdx.x);
 }
 
 __device__ __forceinline__ void select_count_body(const float* __restrict__ scores, int n,
@@ -204,10 +214,13 @@ __global__ __launch_bounds__(kScanThreads) void select_scan(const uint32_t* __re
     block_exclusive_scan(tile_cnt, tile_off, ntiles);
 }
 
-// off_from_scan: the tile offsets come from select_scan (many tiles) instead
-// of a per-block sum of the preceding tiles' counts.
+// Equal keys before this tile: from the last pass's rows when given, else
+// from select_scan (off_from_scan, many tiles) or the preceding tiles'
+// select_count totals.  Not needed (and not read) when no key equal to T is
+// pruned.
 __device__ __forceinline__ void select_mask_body(const float* __restrict__ scores, int n,
                                                         const SelectState* __restrict__ st,
+                                                        const uint32_t* __restrict__ rows,
                                                         const uint32_t* __restrict__ tile_cnt,
                                                         const uint32_t* __restrict__ tile_off, int off_from_scan,
                                                         uint8_t* __restrict__ keep, int64_t* __restrict__ d_n_keep,
@@ -220,8 +233,13 @@ __device__ __forceinline__ void select_mask_body(const float* __restrict__ score
         if (d_n_keep) *d_n_keep = st->n_keep;
         if (d_threshold) *d_threshold = T;
     }
-    const int64_t tile_start = off_from_scan ? (int64_t)tile_off[blk]
-                                             : (int64_t)block_sum_prefix(tile_cnt, blk);
+    int64_t tile_start = 0;
+    if (k_eq > 0) {
+        if (rows)
+            tile_start = (int64_t)block_sum_prefix(rows + (T & (kSelectLastBins - 1)), blk, kSelectLastBins);
+        else
+            tile_start = off_from_scan ? (int64_t)tile_off[blk] : (int64_t)block_sum_prefix(tile_cnt, blk);
+    }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int base = blk * kTile;
     uint32_t key[kItems];
@@ -253,12 +271,14 @@ __device__ __forceinline__ void select_mask_body(const float* __restrict__ score
 
 __global__ __launch_bounds__(kBlock) void select_mask(const float* __restrict__ scores, int n,
                                                         const SelectState* __restrict__ st,
+                                                        const uint32_t* __restrict__ rows,
                                                         const uint32_t* __restrict__ tile_cnt,
                                                         const uint32_t* __restrict__ tile_off, int off_from_scan,
                                                         uint8_t* __restrict__ keep, int64_t* __restrict__ d_n_keep,
                                                         uint32_t* __restrict__ d_threshold)
 {
-    select_mask_body(scores, n, st, tile_cnt, tile_off, off_from_scan, keep, d_n_keep, d_threshold, blockIdx.x);
+    select_mask_body(scores, n, st, rows, tile_cnt, tile_off, off_from_scan, keep, d_n_keep, d_threshold,
+                     blockIdx.x);
 }
 
 __global__ void select_outputs(const SelectState* __restrict__ st, int64_t* __restrict__ d_n_keep,
@@ -289,7 +309,8 @@ __global__ __launch_bounds__(kBlock) void select_hist_batch(const BatchJob* __re
     const BatchJob& b = jobs[batch_job_of<true>(jobs, nj, blockIdx.x)];
     if (b.n_prune == 0) return;
     select_hist_body(b.scores, b.n, b.sel, kPassShift[pass], kPassBits[pass],
-                     b.hist + pass * kHistCopies * kHistBins, (int)blockIdx.x - b.tile0);
+                     b.hist + pass * kHistCopies * kHistBins, pass == 2 ? b.tile_rows : nullptr,
+                     (int)blockIdx.x - b.tile0);
 }
 
 __global__ __launch_bounds__(kScanThreads) void select_find_batch(const BatchJob* __restrict__ jobs, int pass)
@@ -300,16 +321,10 @@ __global__ __launch_bounds__(kScanThreads) void select_find_batch(const BatchJob
                      pass == 2 ? 1 : 0);
 }
 
-__global__ __launch_bounds__(kBlock) void select_count_batch(const BatchJob* __restrict__ jobs, int nj)
-{
-    const BatchJob& b = jobs[batch_job_of<true>(jobs, nj, blockIdx.x)];
-    select_count_body(b.scores, b.n, b.sel, b.tile_cnt, (int)blockIdx.x - b.tile0);
-}
-
 __global__ __launch_bounds__(kBlock) void select_mask_batch(const BatchJob* __restrict__ jobs, int nj)
 {
     const BatchJob& b = jobs[batch_job_of<true>(jobs, nj, blockIdx.x)];
-    select_mask_body(b.scores, b.n, b.sel, b.tile_cnt, nullptr, 0, b.keep, b.n_keep_out, nullptr,
+    select_mask_body(b.scores, b.n, b.sel, b.tile_rows, nullptr, nullptr, 0, b.keep, b.n_keep_out, nullptr,
                      (int)blockIdx.x - b.tile0);
 }
 
@@ -322,7 +337,6 @@ hipError_t launch_select_batch(const BatchJob* d_jobs, int n_jobs, int total_til
         hipLaunchKernelGGL(select_hist_batch, dim3(total_tiles), dim3(kBlock), 0, stream, d_jobs, n_jobs, p);
         hipLaunchKernelGGL(select_find_batch, dim3(n_jobs), dim3(kScanThreads), 0, stream, d_jobs, p);
     }
-    hipLaunchKernelGGL(select_count_batch, dim3(total_tiles), dim3(kBlock), 0, stream, d_jobs, n_jobs);
     hipLaunchKernelGGL(select_mask_batch, dim3(total_tiles), dim3(kBlock), 0, stream, d_jobs, n_jobs);
     return hipGetLastError();
 }
@@ -338,21 +352,25 @@ hipError_t launch_select(const float* d_scores, int64_t n, int64_t n_prune, uint
         hipLaunchKernelGGL(select_outputs, dim3(1), dim3(1), 0, stream, ws.sel, d_n_keep, d_threshold);
         return hipGetLastError();
     }
+    // rows exist for up to kPrefixTilesMax tiles; beyond, count and scan
+    const uint32_t* rows = ntiles <= kPrefixTilesMax ? ws.tile_rows : nullptr;
     if (n_prune > 0) {
         for (int p = 0; p < 3; ++p) {
             uint32_t* h = ws.hist + p * kHistCopies * kHistBins;
             hipLaunchKernelGGL(select_hist, dim3(ntiles), dim3(kBlock), 0, stream, d_scores, (int)n, ws.sel,
-                               kPassShift[p], kPassBits[p], h);
+                               kPassShift[p], kPassBits[p], h, p == 2 ? const_cast<uint32_t*>(rows) : nullptr);
             hipLaunchKernelGGL(select_find, dim3(1), dim3(kScanThreads), 0, stream, ws.sel, h, kPassShift[p],
                                kPassBits[p], p == 2 ? 1 : 0);
         }
     }
-    hipLaunchKernelGGL(select_count, dim3(ntiles), dim3(kBlock), 0, stream, d_scores, (int)n, ws.sel, ws.tile_cnt);
-    const int from_scan = ntiles > kPrefixTilesMax ? 1 : 0;
-    if (from_scan)
+    const int from_scan = (n_prune > 0 && !rows) ? 1 : 0;
+    if (from_scan) {
+        hipLaunchKernelGGL(select_count, dim3(ntiles), dim3(kBlock), 0, stream, d_scores, (int)n, ws.sel,
+                           ws.tile_cnt);
         hipLaunchKernelGGL(select_scan, dim3(1), dim3(kScanThreads), 0, stream, ws.tile_cnt, ws.tile_off, ntiles);
-    hipLaunchKernelGGL(select_mask, dim3(ntiles), dim3(kBlock), 0, stream, d_scores, (int)n, ws.sel, ws.tile_cnt,
-                       ws.tile_off, from_scan, d_keep, d_n_keep, d_threshold);
+    }
+    hipLaunchKernelGGL(select_mask, dim3(ntiles), dim3(kBlock), 0, stream, d_scores, (int)n, ws.sel, rows,
+                       ws.tile_cnt, ws.tile_off, from_scan, d_keep, d_n_keep, d_threshold);
     return hipGetLastError();
 }
 

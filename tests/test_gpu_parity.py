@@ -189,6 +189,30 @@ def test_select_edges_and_ties(n_prune):
     assert int(nk.item()) == n - n_prune
 
 
+def test_select_ties_across_tiles_reused_workspace():
+    """Ties at the threshold spread over ~250 tiles (the equal keys before
+    each tile come from the last histogram pass's per-tile rows), on one
+    workspace reused by calls that prune many, none, then a few."""
+    import torch
+
+    from paper_2606_09074_amd import api
+    n = 1_000_003
+    rng = np.random.default_rng(77)
+    vals = (rng.integers(0, 40, size=n) * np.float32(0.25)).astype(np.float32)
+    vals[rng.integers(0, n, size=50)] = -0.0
+    dev = torch.device("cuda:0")
+    s = torch.from_numpy(vals).to(dev)
+    ws = api.workspace(n, 1, dev)
+    for n_prune in (int(n * 0.61) + 5, 0, 123_457, 1):
+        log(f"select ties n={n} n_prune={n_prune}")
+        keep = torch.empty(n, dtype=torch.uint8, device=dev)
+        nk = torch.empty(1, dtype=torch.int64, device=dev)
+        api.refine_select(s, keep, ws, n_prune=n_prune, n_keep_out=nk)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(keep.cpu().numpy(), expected_keep_from_scores(vals, n_prune))
+        assert int(nk.item()) == n - n_prune
+
+
 def test_select_all_equal_scores():
     import torch
 
