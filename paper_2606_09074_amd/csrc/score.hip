@@ -581,7 +581,8 @@ __device__ inline float support(float n0, float n1, float n2, float nn, float hx
     return fminf(fmaf(fabsf(n0), hx, fmaf(fabsf(n1), hy, fabsf(n2) * hz)), rm * nn);
 }
 
-__device__ inline bool cull_pass(const CullRec& q, float cx, float cy, float cz, float hx, float hy, float hz,
+template <class Rec>
+__device__ inline bool cull_pass(const Rec& q, float cx, float cy, float cz, float hx, float hy, float hz,
                                  float rm, float sg, float ca, float z_near)
 {
     const float depth = fmaf(q.nz[0], cx, fmaf(q.nz[1], cy, fmaf(q.nz[2], cz, q.nz[3])));
@@ -670,17 +671,22 @@ __global__ void views_init(unsigned long long* __restrict__ evaluated)
     if (threadIdx.x < kEvalSlots) evaluated[threadIdx.x] = 0ull;
 }
 
-// The views each view-loop group evaluates, as 64-bit masks: a block of 16
-// waves takes 64 groups (their bounds staged in LDS, with the culling
-// records of up to kViewChunk views), each wave 4 of them; lane l holds the
-// culling record of view 64 b + l in registers and tests it against each of
-// the wave's groups in turn.  A view is dropped only when no point of the group's
-// bounds can pass the near plane or one image edge even with the largest
-// footprint any of its primitives can have.  Also counts each group's views
-// into the block's work classes.
-constexpr int kCullThreads = 1024;   // 16 waves share the staged culling records
-constexpr int kCullWaveGroups = 4;
-constexpr int kCullBlockGroups = kCullWaveGroups * (kCullThreads / 64);   // 64
+// The views each view-loop group evaluates, as 64-bit masks.  Lane l of a
+// block holds the bounds of group 64 b + l in registers; its 16 waves split
+// the views into runs of 16, and every view's culling record is wave-uniform,
+// so it comes in through scalar loads and no LDS traffic or cross-lane step
+// is needed per test (the many short runs let the waves hide each other's
+// load latency).  Each wave writes the 16-bit pieces of its runs (pieces past
+// the last view are written as 0).  A view is dropped only when no point
+// of the group's bounds can pass the near plane or one image edge even with
+// the largest footprint any of its primitives can have.  Also counts each
+// group's views into the block's work classes.
+constexpr int kCullWaves = 16;
+constexpr int kCullThreads = 64 * kCullWaves;
+constexpr int kCullBlockGroups = 64;
+constexpr int kCullRun = 16;   // views per run (a run's mask bits are stored as one piece)
+using CullPiece = std::conditional_t<kCullRun == 16, uint16_t, uint32_t>;
+static_assert(kCullRun == 8 * (int)sizeof(CullPiece), "one mask piece per run");
 
 template <int PPL>
 __global__ __launch_bounds__(kCullThreads) void cull_groups(const GroupBound* __restrict__ gb, int ngroups64, int ngroups,
@@ -690,7 +696,7 @@ __global__ __launch_bounds__(kCullThreads) void cull_groups(const GroupBound* __
                                                         unsigned long long* __restrict__ evaluated)
 {
     __shared__ GroupBound sb[kCullBlockGroups];
-    __shared__ CullRec sc[kViewChunk];   // the culling records of up to kViewChunk views (32 KB)
+    __shared__ uint32_t part[kCullWaves][kCullBlockGroups];
     __shared__ uint32_t hist[kOrderBuckets];
     // the class counts are cleared before this kernel (by group_bounds, then
     // by each view loop); the cursors aux[0, kOrderBuckets) and the pair
@@ -699,43 +705,43 @@ __global__ __launch_bounds__(kCullThreads) void cull_groups(const GroupBound* __
         if (threadIdx.x < kOrderBuckets) aux[threadIdx.x] = 0u;
         if (evaluated && threadIdx.x < kEvalSlots) evaluated[threadIdx.x] = 0ull;
     }
-    const int gblock = blockIdx.x * kCullBlockGroups;
-    if (threadIdx.x < kCullBlockGroups && gblock + (int)threadIdx.x < ngroups)
-        sb[threadIdx.x] = loop_group_bound<PPL>(gb, ngroups64, gblock + threadIdx.x);
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    const int G = blockIdx.x * kCullBlockGroups + lane;
+    const bool live = G < ngroups;
+    if (wave == 0) {
+        GroupBound z = {};
+        sb[lane] = live ? loop_group_bound<PPL>(gb, ngroups64, G) : z;
+    }
     if (threadIdx.x < kOrderBuckets) hist[threadIdx.x] = 0u;
     __syncthreads();
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int first = wave * kCullWaveGroups;   // within the block
-    const int nk = min(kCullWaveGroups, ngroups - gblock - first);   // groups of this wave (may be <= 0)
+    const GroupBound g = sb[lane];
+    const float ca = fabsf(g.c[0]) + fabsf(g.c[1]) + fabsf(g.c[2]);
+    // a non-finite bound (non-finite input) disables culling for the group
+    const bool no_cull = !(g.rm < INFINITY) || !(g.sg < INFINITY) || !(ca < INFINITY);
     const int nwords = (nv + 63) / 64;
-    uint32_t cnt = 0;   // lane k < nk: views of group gblock + first + k
-    for (int c0 = 0; c0 < nv; c0 += kViewChunk) {
-    const int cn = min(kViewChunk, nv - c0);
-    __syncthreads();   // the previous chunk's reads are done
-    constexpr int kRecVec = sizeof(CullRec) / sizeof(float4);
-    for (int t = threadIdx.x; t < cn * kRecVec; t += kCullThreads)
-        reinterpret_cast<float4*>(sc)[t] = reinterpret_cast<const float4*>(culls + c0)[t];
-    __syncthreads();
-    for (int b = c0 / 64; b < (c0 + cn + 63) / 64; ++b) {
-        const int v = b * 64 + lane;
-        CullRec q = {};
-        if (v < nv) q = sc[v - c0];
-        for (int k = 0; k < nk; ++k) {
-            const GroupBound g = sb[first + k];
-            const float ca = fabsf(g.c[0]) + fabsf(g.c[1]) + fabsf(g.c[2]);
-            // a non-finite bound (non-finite input) disables culling for the group
-            const bool no_cull = !(g.rm < INFINITY) || !(g.sg < INFINITY) || !(ca < INFINITY);
-            const bool vis = (v < nv) & (no_cull | cull_pass(q, g.c[0], g.c[1], g.c[2], g.h[0], g.h[1], g.h[2], g.rm,
-                                                             g.sg, ca, z_near));
-            const uint64_t m = __ballot(vis);
-            if (lane == 0) mask[(size_t)(gblock + first + k) * nwords + b] = m;
-            if (lane == k) cnt += (uint32_t)__popcll(m);
+    CullPiece* const row = reinterpret_cast<CullPiece*>(mask + (size_t)G * nwords);   // little-endian pieces
+    uint32_t cnt = 0;
+    for (int r = wave; r < (64 / kCullRun) * nwords; r += kCullWaves) {
+        const int v0 = r * kCullRun;
+        const int vn = max(0, min(kCullRun, nv - v0));
+        uint32_t m = 0u;
+        for (int j = 0; j < vn; ++j) {
+            const bool vis = no_cull | cull_pass(culls[v0 + j], g.c[0], g.c[1], g.c[2], g.h[0], g.h[1], g.h[2],
+                                                 g.rm, g.sg, ca, z_near);
+            m |= vis ? 1u << j : 0u;
         }
+        if (live) row[r] = (CullPiece)m;
+        cnt += (uint32_t)__popc(m);
     }
-    }
-    if (lane < nk) {
-        counts[gblock + first + lane] = cnt;
-        atomicAdd(&hist[work_class(cnt, nv)], 1u);
+    part[wave][lane] = cnt;
+    __syncthreads();
+    if (wave == 0 && live) {
+        uint32_t total = 0;
+#pragma unroll
+        for (int w = 0; w < kCullWaves; ++w) total += part[w][lane];
+        counts[G] = total;
+        atomicAdd(&hist[work_class(total, nv)], 1u);
     }
     __syncthreads();
     if (threadIdx.x < kOrderBuckets && hist[threadIdx.x])
