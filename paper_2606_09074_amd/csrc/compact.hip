@@ -357,12 +357,6 @@ void launch_compact_t(const E* in, int64_t in_stride, int n, const uint8_t* d_ke
 // Grouped launches over the jobs of a batch.  The tile offsets come from the
 // per-block sums of the job's preceding tiles (jobs of a batch have at most
 // kPrefixTilesMax tiles).
-__global__ __launch_bounds__(kBlock) void compact_count_batch(const BatchJob* __restrict__ jobs, int nj)
-{
-    const BatchJob& b = jobs[batch_job_of<true>(jobs, nj, blockIdx.x)];
-    compact_count_body(b.keep, b.n, b.tile_cnt, (int)blockIdx.x - b.tile0);
-}
-
 template <class E>
 __device__ __forceinline__ void compact_job_tile(const BatchJob& b, int tile)
 {
@@ -389,9 +383,10 @@ __global__ __launch_bounds__(kBlock) void compact_scatter_batch(const BatchJob* 
 
 }  // namespace
 
+// The batch's selection has stored every tile's survivor count (the mask
+// pass counts them), so no counting pass is needed here.
 hipError_t launch_compact_batch(const BatchJob* d_jobs, int n_jobs, int total_tiles, hipStream_t stream)
 {
-    hipLaunchKernelGGL(compact_count_batch, dim3(total_tiles), dim3(kBlock), 0, stream, d_jobs, n_jobs);
     hipLaunchKernelGGL(compact_scatter_batch, dim3(total_tiles), dim3(kBlock), 0, stream, d_jobs, n_jobs);
     return hipGetLastError();
 }

@@ -224,9 +224,11 @@ __device__ __forceinline__ void select_mask_body(const float* __restrict__ score
                                                         const uint32_t* __restrict__ tile_cnt,
                                                         const uint32_t* __restrict__ tile_off, int off_from_scan,
                                                         uint8_t* __restrict__ keep, int64_t* __restrict__ d_n_keep,
-                                                        uint32_t* __restrict__ d_threshold, int blk)
+                                                        uint32_t* __restrict__ d_threshold, int blk,
+                                                        uint32_t* __restrict__ kept_cnt = nullptr)
 {
     __shared__ uint32_t cnt[kItems][kWaves];
+    __shared__ uint32_t kept_red[kWaves];
     const uint32_t T = st->threshold;
     const int64_t k_eq = st->k_eq;
     if (blk == 0 && threadIdx.x == 0) {
@@ -253,6 +255,7 @@ __device__ __forceinline__ void select_mask_body(const float* __restrict__ score
     }
     __syncthreads();
     int64_t row = tile_start;
+    uint32_t kept = 0;
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
         const int i = base + k * kBlock + (int)threadIdx.x;
@@ -265,7 +268,18 @@ __device__ __forceinline__ void select_mask_body(const float* __restrict__ score
         const int64_t eq_rank = row + before + lanes_below(eqb[k]);
         const bool pruned = key[k] < T || (key[k] == T && eq_rank < k_eq);
         if (i < n) keep[i] = pruned ? 0 : 1;
+        kept += (i < n && !pruned) ? 1u : 0u;
         row += tot;
+    }
+    if (kept_cnt) {   // survivors of the tile, for a compaction that follows in the same launch sequence
+        kept = wave_sum_u32(kept);
+        if (lane == 0) kept_red[wave] = kept;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t t = 0;
+            for (int w = 0; w < kWaves; ++w) t += kept_red[w];
+            kept_cnt[blk] = t;
+        }
     }
 }
 
@@ -324,8 +338,9 @@ __global__ __launch_bounds__(kScanThreads) void select_find_batch(const BatchJob
 __global__ __launch_bounds__(kBlock) void select_mask_batch(const BatchJob* __restrict__ jobs, int nj)
 {
     const BatchJob& b = jobs[batch_job_of<true>(jobs, nj, blockIdx.x)];
+    // also stores each tile's survivor count, which the batch's compaction uses
     select_mask_body(b.scores, b.n, b.sel, b.tile_rows, nullptr, nullptr, 0, b.keep, b.n_keep_out, nullptr,
-                     (int)blockIdx.x - b.tile0);
+                     (int)blockIdx.x - b.tile0, b.tile_cnt);
 }
 
 }  // namespace
