@@ -64,6 +64,19 @@ struct SelectState {
     uint32_t pad[7];
 };
 
+// The state a selection starts from (the threshold search has resolved no
+// bits yet and looks for rank n_prune - 1).
+__host__ __device__ inline SelectState select_start(int64_t n, int64_t n_prune)
+{
+    SelectState s = {};
+    s.n = n;
+    s.n_prune = n_prune;
+    s.rank = n_prune - 1;
+    s.k_eq = 0;
+    s.n_keep = n - n_prune;
+    return s;
+}
+
 // Conservative view-frustum test data of one view (fp32, 128 bytes): the
 // world-space half-spaces every visible primitive's centre must satisfy,
 // given a bound on its footprint radius.  Built by camera_prep.

@@ -24,7 +24,8 @@
 // kPrefixTilesMax tiles count per tile and scan in separate launches.)
 //
 // Launches: init, 3 x (histogram, find), mask -- once per call, or once for
-// all the jobs of a batch (select_*_batch, the same bodies).
+// all the jobs of a batch (select_*_batch, the same bodies; there the init
+// rides in the statistics finalisation).
 #include "refine_internal.hpp"
 
 namespace refine {
@@ -40,18 +41,7 @@ __global__ void select_init(SelectState* __restrict__ st, uint32_t* __restrict__
 {
     for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < kSelectHistWords; b += gridDim.x * blockDim.x)
         hist[b] = 0u;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        SelectState s = {};
-        s.n = n;
-        s.n_prune = n_prune;
-        s.rank = n_prune - 1;
-        s.k_eq = 0;
-        s.n_keep = n - n_prune;
-        s.prefix = 0u;
-        s.mask = 0u;
-        s.threshold = 0u;
-        *st = s;
-    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) *st = select_start(n, n_prune);
 }
 
 // Locate the bucket holding the target rank in this pass's histogram (the
@@ -303,20 +293,9 @@ __global__ void select_outputs(const SelectState* __restrict__ st, int64_t* __re
 }
 
 // Grouped launches over the jobs of a batch (jobs that prune nothing skip the
-// histogram passes, as the single-job launch sequence does).
-__global__ __launch_bounds__(kBlock) void select_init_batch(const BatchJob* __restrict__ jobs)
-{
-    const BatchJob& b = jobs[blockIdx.x];
-    for (int w = threadIdx.x; w < kSelectHistWords; w += kBlock) b.hist[w] = 0u;
-    if (threadIdx.x == 0) {
-        SelectState s = {};
-        s.n = b.n;
-        s.n_prune = b.n_prune;
-        s.rank = b.n_prune - 1;
-        s.n_keep = b.n - b.n_prune;
-        *b.sel = s;
-    }
-}
+// histogram passes, as the single-job launch sequence does).  Each job's
+// state and histograms are set up by the batch's statistics finalisation,
+// which runs one block per job earlier in the same launch sequence.
 
 __global__ __launch_bounds__(kBlock) void select_hist_batch(const BatchJob* __restrict__ jobs, int nj, int pass)
 {
@@ -347,7 +326,6 @@ __global__ __launch_bounds__(kBlock) void select_mask_batch(const BatchJob* __re
 
 hipError_t launch_select_batch(const BatchJob* d_jobs, int n_jobs, int total_tiles, hipStream_t stream)
 {
-    hipLaunchKernelGGL(select_init_batch, dim3(n_jobs), dim3(kBlock), 0, stream, d_jobs);
     for (int p = 0; p < 3; ++p) {
         hipLaunchKernelGGL(select_hist_batch, dim3(total_tiles), dim3(kBlock), 0, stream, d_jobs, n_jobs, p);
         hipLaunchKernelGGL(select_find_batch, dim3(n_jobs), dim3(kScanThreads), 0, stream, d_jobs, p);

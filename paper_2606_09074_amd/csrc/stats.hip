@@ -309,10 +309,15 @@ __global__ __launch_bounds__(kBlock) void stats_partial_batch(const BatchJob* __
         stats_partial_body<kStoreBF16F16>(b.planes, b.stride, b.n, eta, b.stat_part, tile);
 }
 
+// Also sets up each job's selection (its state and cleared histograms): the
+// selection passes come later in the batch's launch sequence, and one launch
+// fewer matters for batches of small scenes.
 __global__ __launch_bounds__(kBlock) void stats_finalize_batch(const BatchJob* __restrict__ jobs, refine_params prm)
 {
     const BatchJob& b = jobs[blockIdx.x];
     stats_finalize_body(b.stat_part, (int)num_tiles(b.n), b.n, prm, b.stats);
+    for (int w = threadIdx.x; w < kSelectHistWords; w += kBlock) b.hist[w] = 0u;
+    if (threadIdx.x == 0) *b.sel = select_start(b.n, b.n_prune);
 }
 
 }  // namespace
