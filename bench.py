@@ -30,6 +30,8 @@ if ROOT not in sys.path:
 # primitive (FLOP; FMA = 2, mul/add/rcp/sqrt = 1, compares/min/max = 0), and
 # bytes per primitive (14 fp32 attribute planes read, one fp32 score written).
 FLOP_PER_PAIR = {0: 103, 1: 25, 2: 22}
+# a pair screened out after its first step: camera-space centre 18, d z 4, bound 1
+FLOP_PER_SCREENED_PAIR = 23
 BYTES_PER_PRIM = 14 * 4 + 4
 PEAK_FP32_TFLOPS = 157.3      # MI355X dense FP32 vector, vendor figure
 # VALU issue: 256 CU x 4 SIMD x 2.4 GHz / 2 cycles per wave64 FP32 instruction
@@ -210,16 +212,18 @@ def main() -> int:
     avg["views"] = float(np.mean(views_ms))
     log(f"bench: {ms_per_step:.3f} ms/step, phases {avg}")
 
-    # pairs the view loop evaluated in full (culled pairs excluded), read once after the timed region
-    evaluated = torch.zeros(1, dtype=torch.int64, device=dev)
+    # pairs the view loop evaluated in full, and pairs it screened out after
+    # their first step (culled pairs are in neither), read once after the timed region
+    evaluated = torch.zeros(2, dtype=torch.int64, device=dev)
     api.refine_score_views(planes, V, st, scores, ws, params, evaluated_out=evaluated, stream=stream)
     torch.cuda.synchronize()
-    n_eval = int(evaluated.item())
+    n_eval, n_screened = (int(x) for x in evaluated.cpu().tolist())
 
     # roofline of the view loop (the dominant kernel): ALU-bound FP32 work it
     # actually performed, over its event-timed duration
     t_views = avg["views"] / 1e3
-    achieved_tflops = FLOP_PER_PAIR[params.proj_mode] * n_eval / t_views / 1e12
+    flops = FLOP_PER_PAIR[params.proj_mode] * n_eval + FLOP_PER_SCREENED_PAIR * n_screened
+    achieved_tflops = flops / t_views / 1e12
     kname = "score_binned" if n_eval < n * V else "score_direct"
     counters = profiled_counters(kname, spec.name) if params.proj_mode == 0 else {}
     traffic = counters.get("hbm_bytes_per_launch")
@@ -233,6 +237,7 @@ def main() -> int:
                 "achieved": round(achieved_tflops, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved_tflops / PEAK_FP32_TFLOPS, 4), "traffic": traffic, "valu_issue": valu_issue,
                 "flop_per_pair": FLOP_PER_PAIR[params.proj_mode], "pairs_evaluated": n_eval,
+                "flop_per_screened_pair": FLOP_PER_SCREENED_PAIR, "pairs_screened": n_screened,
                 "pairs_total": n * V, "views_ms": round(avg["views"], 4), "prepare_ms": round(avg["prepare"], 4)}
     cpu = None
     if not args.no_cpu_baseline:

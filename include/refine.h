@@ -226,9 +226,12 @@ refine_status refine_score(const refine_scene* scene, const float* d_cams, int32
  *                        and d_stats must be passed (scene->planes is read
  *                        only on the direct path).  Several views calls may
  *                        follow one prepare.
- *  d_evaluated (nullable, device int64) receives the number of pairs the
- *  view loop evaluated in full (n * |V| on the direct path; on the binned
- *  path, pairs of 64-primitive groups whose bound reaches the view).
+ *  d_evaluated (nullable, device int64[2]) receives [0] the number of pairs
+ *  the view loop evaluated in full and [1] the number it screened out after
+ *  their first step (the camera-space centre and its distance outside the
+ *  image), because no record of their group could pass for that view.
+ *  On the direct path these are n * |V| and 0. On the binned path, [0] + [1]
+ *  counts the pairs of 64-primitive groups whose bound reaches the view.
  */
 refine_status refine_score_prepare(const refine_scene* scene, const float* d_cams, int32_t n_views,
                                    const refine_params* params, const refine_stats_t* d_stats,

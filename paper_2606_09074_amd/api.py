@@ -139,8 +139,9 @@ def refine_score_views(planes: torch.Tensor, n_views: int, stats: torch.Tensor, 
     sc = _scene(planes, n)
     if scores_out.dtype != torch.float32 or scores_out.numel() < sc.n or not scores_out.is_cuda:
         raise ValueError("scores_out must be a float32 GPU tensor of at least n elements")
-    if evaluated_out is not None and (evaluated_out.dtype != torch.int64 or not evaluated_out.is_cuda):
-        raise ValueError("evaluated_out must be an int64 GPU tensor")
+    if evaluated_out is not None and (evaluated_out.dtype != torch.int64 or not evaluated_out.is_cuda
+                                      or evaluated_out.numel() < 2):
+        raise ValueError("evaluated_out must be an int64 GPU tensor of 2 elements (evaluated, screened)")
     check(_lib.load().refine_score_views(ctypes.byref(sc), int(n_views), ctypes.byref(params), _ptr(stats),
                                          _ptr(scores_out), _ptr(evaluated_out), _ptr(ws), ws.numel(),
                                          _stream_ptr(stream)), "refine_score_views")

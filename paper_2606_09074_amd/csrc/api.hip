@@ -89,7 +89,7 @@ size_t workspace_layout(int64_t n, int32_t n_views, bool score, void* base, Work
     // prefix only; the camera tables come last, so that no other section's
     // place depends on the number of views (a workspace prepared for one
     // camera set keeps its binned scene when the tables are rebuilt)
-    const size_t o_eval = off;  off += score ? align_up(sizeof(unsigned long long) * kEvalSlots) : 0;
+    const size_t o_eval = off;  off += score ? align_up(sizeof(unsigned long long) * 2 * kEvalSlots) : 0;
     const size_t o_ccnt = off;  off += score ? align_up(sizeof(uint32_t) * kCells * kBinCopies) : 0;
     const size_t o_ccur = off;  off += score ? align_up(sizeof(uint32_t) * kCells * kBinCopies) : 0;
     const size_t o_dest = off;  off += score ? align_up(sizeof(uint32_t) * (size_t)n) : 0;

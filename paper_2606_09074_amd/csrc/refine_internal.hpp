@@ -47,7 +47,8 @@ struct CamRec {
     float cx0, cx1;    // EWA clamp interval of X / z: ox -+ sv clamp_k W/2
     float cy0, cy1;    // of Y / z: oy -+ sv clamp_k H/2
     float hw, hh;      // sv W/2, sv H/2
-    float pad[14];
+    float kvs;         // 3 (1 + margin) sv kv: a pair whose footprint can reach the image has d z < kvs s_max
+    float pad[13];
 };
 static_assert(sizeof(CamRec) == kCamRec * sizeof(float), "camera record size");
 
@@ -146,7 +147,7 @@ struct Workspace {
     uint32_t* gcount;        // [num_groups(n, kGroup)] views each view-loop group evaluates
     uint32_t* gaux;          // [kOrderAuxWords] work-class cursors and counts
     uint64_t* gmask;         // [num_groups(n, kGroup)][ceil(n_views / 64)] views each group evaluates
-    unsigned long long* evaluated;   // [kEvalSlots] pairs evaluated by the last view loop
+    unsigned long long* evaluated;   // [2][kEvalSlots] pairs evaluated in full / screened out by the last view loop
 };
 
 __host__ __device__ inline int64_t num_tiles(int64_t n) { return (n + kTile - 1) / kTile; }

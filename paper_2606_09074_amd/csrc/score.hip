@@ -98,8 +98,13 @@ __device__ __forceinline__ void camera_prep_body(const float* __restrict__ cams,
     r.cx1 = ox + lx;
     r.cy0 = oy - ly;
     r.cy1 = oy + ly;
+    {
+        // the culling bound of the footprint in the scaled units of this record
+        const float limx = clamp_k * W / (2.0f * fx), limy = clamp_k * H / (2.0f * fy);
+        r.kvs = sv * (3.0f * kCullMargin * sqrtf(fx * fx * (1.0f + limx * limx) + fy * fy * (1.0f + limy * limy)));
+    }
 #pragma unroll
-    for (int k = 0; k < 14; ++k) r.pad[k] = 0.0f;
+    for (int k = 0; k < 13; ++k) r.pad[k] = 0.0f;
     out[j] = r;
     if (!cull) return;
 
@@ -154,10 +159,10 @@ struct Prim {
 // vector registers.
 struct CamEval {
     float px[4], py[4], pz[4];
-    float cx0, cx1, cy0, cy1, hw, hh;
+    float cx0, cx1, cy0, cy1, hw, hh, kvs;
 };
 constexpr int kStageVec = 5;   // float4s staged per view
-static_assert(offsetof(CamRec, hh) + sizeof(float) <= kStageVec * sizeof(float4), "staged camera fields");
+static_assert(offsetof(CamRec, kvs) + sizeof(float) <= kStageVec * sizeof(float4), "staged camera fields");
 
 // Activation (Sec. 3.1 readings) of primitive i; pre is the epilogue factor.
 template <int ST>
@@ -205,17 +210,41 @@ __device__ inline void activate(const void* __restrict__ planes, int64_t stride,
     if (proj == REFINE_PROJ_COV) pre = pre / (3.0f * ssq);   // 1 / (9 sbar^2): L carries 3
 }
 
-template <int PROJ, class Cam>
-__device__ __forceinline__ void eval_pair(const Cam& c, Prim& p, float eta, float z_near)
+// The first part of a pair's evaluation: the camera-space centre and d z.
+struct PairHead {
+    float X, Y, z, dz;
+};
+
+template <class Cam>
+__device__ __forceinline__ PairHead pair_head(const Cam& c, const Prim& p)
 {
-    const float X = fmaf(c.px[0], p.mx, fmaf(c.px[1], p.my, fmaf(c.px[2], p.mz, c.px[3])));
-    const float Y = fmaf(c.py[0], p.mx, fmaf(c.py[1], p.my, fmaf(c.py[2], p.mz, c.py[3])));
-    const float z = fmaf(c.pz[0], p.mx, fmaf(c.pz[1], p.my, fmaf(c.pz[2], p.mz, c.pz[3])));
+    PairHead hd;
+    hd.X = fmaf(c.px[0], p.mx, fmaf(c.px[1], p.my, fmaf(c.px[2], p.mz, c.px[3])));
+    hd.Y = fmaf(c.py[0], p.mx, fmaf(c.py[1], p.my, fmaf(c.py[2], p.mz, c.py[3])));
+    hd.z = fmaf(c.pz[0], p.mx, fmaf(c.pz[1], p.my, fmaf(c.pz[2], p.mz, c.pz[3])));
+    // d z with d = max(|ux| - hw, |uy| - hh) (z > 0 wherever it matters)
+    hd.dz = fmaxf(fmaf(-c.hw, hd.z, fabsf(hd.X)), fmaf(-c.hh, hd.z, fabsf(hd.Y)));
+    return hd;
+}
+
+// Whether the pair can pass the gate at all: the footprint radius r obeys
+// r z <= 3 s_max |z J R_v|_2 <= kvs s_max / (1 + margin) under the clamp, so a
+// pair with d z >= kvs s_max (or behind the near plane) adds exactly +0.
+// Written so that a NaN bound or d z counts as "can pass".
+__device__ __forceinline__ bool pair_may_pass(const PairHead& hd, float kvs, float smax, float z_near)
+{
+    return (hd.z > z_near) && !(hd.dz >= kvs * smax);
+}
+
+template <int PROJ, class Cam>
+__device__ __forceinline__ void pair_tail(const Cam& c, Prim& p, const PairHead& hd, float eta, float z_near)
+{
+    const float z = hd.z, dz = hd.dz;
     const float zz = fmaf(z, z, eta);
     const float q = __builtin_amdgcn_rcpf(z * zz);
     const float rz = q * zz;
-    const float ux = X * rz;
-    const float uy = Y * rz;
+    const float ux = hd.X * rz;
+    const float uy = hd.Y * rz;
     const float xh = __builtin_amdgcn_fmed3f(ux, c.cx0, c.cx1);
     const float yh = __builtin_amdgcn_fmed3f(uy, c.cy0, c.cy1);
     const float r00 = fmaf(-xh, c.pz[0], c.px[0]);
@@ -241,8 +270,6 @@ __device__ __forceinline__ void eval_pair(const Cam& c, Prim& p, float eta, floa
         P = q * z;
     else
         P = 1.0f;
-    // d z with d = max(|ux| - hw, |uy| - hh) (z > 0 wherever it matters)
-    const float dz = fmaxf(fmaf(-c.hw, z, fabsf(X)), fmaf(-c.hh, z, fabsf(Y)));
     // With L scaled by 3, sa, sb, sc are 9 a, 9 b, 9 c, and the footprint
     // test (d z)^2 < 4.5 (a + c + sqrt((a - c)^2 + 4 b^2)) reads
     // g < (sa + sc)/2 + sqrt(((sa - sc)/2)^2 + sb^2) with g = (d z)^2; with
@@ -255,6 +282,12 @@ __device__ __forceinline__ void eval_pair(const Cam& c, Prim& p, float eta, floa
     // whenever dz is, and fminf returns the other operand when one is NaN
     const bool g = (z > z_near) && (fminf(dz, fminf(u + v, h)) < 0.0f);
     p.S += g ? P : 0.0f;
+}
+
+template <int PROJ, class Cam>
+__device__ __forceinline__ void eval_pair(const Cam& c, Prim& p, float eta, float z_near)
+{
+    pair_tail<PROJ>(c, p, pair_head(c, p), eta, z_near);
 }
 
 template <int PROJ, int ST>
@@ -608,7 +641,7 @@ __device__ __forceinline__ void load_cam(const float4* __restrict__ r, CamEval& 
     c.py[0] = r1.x; c.py[1] = r1.y; c.py[2] = r1.z; c.py[3] = r1.w;
     c.pz[0] = r2.x; c.pz[1] = r2.y; c.pz[2] = r2.z; c.pz[3] = r2.w;
     c.cx0 = r3.x; c.cx1 = r3.y; c.cy0 = r3.z; c.cy1 = r3.w;
-    c.hw = r4.x; c.hh = r4.y;
+    c.hw = r4.x; c.hh = r4.y; c.kvs = r4.z;
 }
 
 constexpr int kViewChunk = 256;   // views staged in LDS at a time (20 KB)
@@ -668,7 +701,7 @@ __device__ inline int work_class(uint32_t cnt, int nv)
 // Clears the pair counters when the view loop does not run (n = 0).
 __global__ void views_init(unsigned long long* __restrict__ evaluated)
 {
-    if (threadIdx.x < kEvalSlots) evaluated[threadIdx.x] = 0ull;
+    if (threadIdx.x < 2 * kEvalSlots) evaluated[threadIdx.x] = 0ull;
 }
 
 // The views each view-loop group evaluates, as 64-bit masks.  Lane l of a
@@ -703,7 +736,7 @@ __global__ __launch_bounds__(kCullThreads) void cull_groups(const GroupBound* __
     // counters are used only by the kernels after it
     if (blockIdx.x == 0) {
         if (threadIdx.x < kOrderBuckets) aux[threadIdx.x] = 0u;
-        if (evaluated && threadIdx.x < kEvalSlots) evaluated[threadIdx.x] = 0ull;
+        if (evaluated && threadIdx.x < 2 * kEvalSlots) evaluated[threadIdx.x] = 0ull;
     }
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
@@ -809,7 +842,7 @@ __global__ __launch_bounds__(kBlock) void score_binned(const PrimRec* __restrict
     const int G = active ? min(max(__builtin_amdgcn_readfirstlane(order[w]), 0), ngroups - 1) : 0;
     const int g0 = G * kGroup * PPL;
     Prim p[PPL];
-    float pre[PPL];
+    float pre[PPL], smax[PPL];
     int idx[PPL];
 #pragma unroll
     for (int k = 0; k < PPL; ++k) {
@@ -817,6 +850,7 @@ __global__ __launch_bounds__(kBlock) void score_binned(const PrimRec* __restrict
         const int jj = min(j, n - 1);   // lanes past the end repeat the last record
         const PrimRec r = recs[jj];
         p[k].mx = r.mu[0]; p[k].my = r.mu[1]; p[k].mz = r.mu[2];
+        smax[k] = r.smax;
         p[k].L00 = r.L[0]; p[k].L01 = r.L[1]; p[k].L02 = r.L[2];
         p[k].L10 = r.L[3]; p[k].L11 = r.L[4]; p[k].L12 = r.L[5];
         p[k].L20 = r.L[6]; p[k].L21 = r.L[7]; p[k].L22 = r.L[8];
@@ -830,7 +864,7 @@ __global__ __launch_bounds__(kBlock) void score_binned(const PrimRec* __restrict
     // the whole block, so that every camera operand of the pair arithmetic
     // is a vector register (an instruction may read only one scalar register)
     __shared__ float4 table[kViewChunk * kStageVec];
-    uint32_t n_eval = 0;
+    uint32_t n_eval = 0, n_screened = 0;   // kept views evaluated in full / screened out
     for (int c0 = 0; c0 < nv; c0 += kViewChunk) {
         const int cn = min(kViewChunk, nv - c0);
         __syncthreads();   // the previous chunk's reads are done
@@ -839,25 +873,56 @@ __global__ __launch_bounds__(kBlock) void score_binned(const PrimRec* __restrict
         __syncthreads();
         for (int v0 = c0; v0 < c0 + cn; v0 += 64) {
             uint64_t m = active ? gm[v0 / 64] : 0ull;
-            n_eval += (uint32_t)__popcll(m);
             while (m != 0ull) {
                 const int b = __builtin_ctzll(m);
                 m &= m - 1ull;
                 CamEval c;
                 load_cam(table + (v0 - c0 + b) * kStageVec, c);
+                // screen: when no record of the group can pass for this view,
+                // all its terms are exactly +0 and the rest is skipped
+                PairHead hd[PPL];
+                bool may = false;
+#pragma unroll
+                for (int k = 0; k < PPL; ++k) {
+                    hd[k] = pair_head(c, p[k]);
+                    may = may || pair_may_pass(hd[k], c.kvs, smax[k], z_near);
+                }
+                const bool live = __ballot(may) != 0ull;
                 if (VPI == 2 && m != 0ull) {
                     const int b2 = __builtin_ctzll(m);
                     m &= m - 1ull;
                     CamEval c2;
                     load_cam(table + (v0 - c0 + b2) * kStageVec, c2);
+                    PairHead hd2[PPL];
+                    bool may2 = false;
 #pragma unroll
                     for (int k = 0; k < PPL; ++k) {
-                        eval_pair<PROJ>(c, p[k], eta, z_near);
-                        eval_pair<PROJ>(c2, p[k], eta, z_near);
+                        hd2[k] = pair_head(c2, p[k]);
+                        may2 = may2 || pair_may_pass(hd2[k], c2.kvs, smax[k], z_near);
+                    }
+                    const bool live2 = __ballot(may2) != 0ull;
+                    n_eval += (live ? 1u : 0u) + (live2 ? 1u : 0u);
+                    n_screened += (live ? 0u : 1u) + (live2 ? 0u : 1u);
+                    if (live && live2) {
+#pragma unroll
+                        for (int k = 0; k < PPL; ++k) {   // each record still adds its views in order
+                            pair_tail<PROJ>(c, p[k], hd[k], eta, z_near);
+                            pair_tail<PROJ>(c2, p[k], hd2[k], eta, z_near);
+                        }
+                    } else if (live) {
+#pragma unroll
+                        for (int k = 0; k < PPL; ++k) pair_tail<PROJ>(c, p[k], hd[k], eta, z_near);
+                    } else if (live2) {
+#pragma unroll
+                        for (int k = 0; k < PPL; ++k) pair_tail<PROJ>(c2, p[k], hd2[k], eta, z_near);
                     }
                 } else {
+                    n_eval += live ? 1u : 0u;
+                    n_screened += live ? 0u : 1u;
+                    if (live) {
 #pragma unroll
-                    for (int k = 0; k < PPL; ++k) eval_pair<PROJ>(c, p[k], eta, z_near);
+                        for (int k = 0; k < PPL; ++k) pair_tail<PROJ>(c, p[k], hd[k], eta, z_near);
+                    }
                 }
             }
         }
@@ -869,14 +934,21 @@ __global__ __launch_bounds__(kBlock) void score_binned(const PrimRec* __restrict
         const int valid = max(0, min(kGroup * PPL, n - g0));   // records of this group
         const int slot = G % kEvalSlots;   // spread: one address would serialise the waves
         atomicAdd(evaluated + slot, (unsigned long long)n_eval * (unsigned long long)valid);
+        atomicAdd(evaluated + kEvalSlots + slot, (unsigned long long)n_screened * (unsigned long long)valid);
     }
 }
 
+// out[0]: pairs evaluated in full, out[1]: pairs screened out after their
+// first step (the direct path evaluates every pair).
 __global__ void counter_store(const unsigned long long* c, int64_t* out, int64_t direct_pairs)
 {
-    unsigned long long t = 0;
-    for (int s = 0; s < kEvalSlots; ++s) t += c[s];
-    *out = direct_pairs >= 0 ? direct_pairs : (int64_t)t;
+    unsigned long long t = 0, sc = 0;
+    for (int s = 0; s < kEvalSlots; ++s) {
+        t += c[s];
+        sc += c[kEvalSlots + s];
+    }
+    out[0] = direct_pairs >= 0 ? direct_pairs : (int64_t)t;
+    out[1] = direct_pairs >= 0 ? 0 : (int64_t)sc;
 }
 
 template <int PROJ, int ST>
@@ -1016,7 +1088,7 @@ hipError_t launch_score_views(const void* planes, int st, int64_t stride, int64_
     const bool binned = binned_path(prm, n);
     unsigned long long* counter = (d_evaluated && binned) ? ws.evaluated : nullptr;
     if (binned && n == 0 && counter)   // the view loop, which clears the pair counters, does not run
-        hipLaunchKernelGGL(views_init, dim3(1), dim3(kEvalSlots), 0, stream, counter);
+        hipLaunchKernelGGL(views_init, dim3(1), dim3(2 * kEvalSlots), 0, stream, counter);
     if (n > 0)
         dispatch_mode(prm.proj_mode, st, [&](auto proj_c, auto st_c) {
             views_mode<decltype(proj_c)::value, decltype(st_c)::value>(planes, stride, (int)n, prm, d_stats, d_scores,

@@ -370,8 +370,9 @@ def test_stats_bounding_box():
 @pytest.mark.parametrize("path", [1, 2])
 def test_two_phase_scoring(path):
     """refine_score_prepare + refine_score_views (twice) equals refine_score;
-    the evaluated-pair count is n |V| on the direct path and at most that,
-    but positive, on the binned path."""
+    the counts: n |V| evaluated and none screened on the direct path; on the
+    binned path some of each, together fewer than n |V| (culled pairs are
+    in neither)."""
     import torch
 
     from paper_2606_09074_amd import _lib, api
@@ -387,18 +388,18 @@ def test_two_phase_scoring(path):
     prm = gpu_params(score_path=path)
     api.refine_stats(pl, st, ws, prm)
     api.refine_score_prepare(pl, cm, st, ws, prm)
-    ev = torch.full((1,), -1, dtype=torch.int64, device=dev)
+    ev = torch.full((2,), -1, dtype=torch.int64, device=dev)
     for _ in range(2):
         out = torch.full((n,), float("nan"), dtype=torch.float32, device=dev)
         api.refine_score_views(pl, cams.shape[0], st, out, ws, prm, evaluated_out=ev)
         np.testing.assert_array_equal(out.cpu().numpy().view(np.uint32), ref.view(np.uint32))
     total = n * cams.shape[0]
-    got = int(ev.item())
-    log(f"[two-phase path={path}] evaluated {got} of {total} pairs ({got / total:.3f})")
+    got, screened = (int(x) for x in ev.cpu().tolist())
+    log(f"[two-phase path={path}] evaluated {got}, screened {screened} of {total} pairs ({got / total:.3f})")
     if path == 1:
-        assert got == total
+        assert got == total and screened == 0
     else:
-        assert 0 < got < total
+        assert 0 < got and 0 < screened and got + screened < total
 
 
 @pytest.mark.parametrize("n,stride,mask_offset,cap_frac", [(9000, 9000, 0, 1.0), (8999, 9000, 0, 1.0),
