@@ -47,7 +47,7 @@ struct CamRec {
     float cx0, cx1;    // EWA clamp interval of X / z: ox -+ sv clamp_k W/2
     float cy0, cy1;    // of Y / z: oy -+ sv clamp_k H/2
     float hw, hh;      // sv W/2, sv H/2
-    float kvs;         // 3 (1 + margin) sv kv: a pair whose footprint can reach the image has d z < kvs s_max
+    float kvs;         // sv kv3: a pair whose footprint can reach the image has d z < kvs s_max
     float pad[13];
 };
 static_assert(sizeof(CamRec) == kCamRec * sizeof(float), "camera record size");
@@ -85,7 +85,7 @@ struct CullRec {
     float nz[4];        // R_v row 2, t_z: depth = nz . mu + nz[3]
     float side[4][4];   // per image edge: n (3), d; visible => n . mu + d + 3 s_max kv > 0
     float nn[4];        // |n| of each side
-    float kv3;          // 3 (1 + margin) sqrt(fx^2 (1 + lim_x^2) + fy^2 (1 + lim_y^2))
+    float kv3;          // 3 (1 + margin) max |z J|_2 over the clamp box (footprint: r z <= kv3 s_max)
     float pad[7];
 };
 static_assert(sizeof(CullRec) == 32 * sizeof(float), "cull record size");

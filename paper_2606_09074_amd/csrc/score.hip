@@ -51,8 +51,8 @@
 // Binned path, per camera set: cull_groups gives every group the set of
 // views it evaluates: a view is dropped only when no point of the group's
 // bounds can pass the near plane or one image edge even with the largest
-// footprint any of its primitives can have, r <= 3 s_max |J|_F (the clamp
-// bounds |J|_F z by kv), inflated by a 1% margin, so every dropped pair
+// footprint any of its primitives can have, r <= 3 s_max |J|_2 (the clamp
+// bounds the spectral norm |z J|_2 by kv), inflated by a 1% margin, so every dropped pair
 // would have added exactly +0 and both paths give bit-identical scores.
 // place_groups orders the groups by how many views they keep (most first,
 // so no long group runs alone at the end), and score_binned gives each wave
@@ -70,6 +70,20 @@ constexpr float kCullMargin = 1.01f;
 constexpr int64_t kBinnedMinPrims = 65536;
 constexpr int kDefaultPPL = 2;   // binned records per lane unless the caller picks (2: half the culling tests)
 constexpr int kDefaultVPI = 1;   // views per iteration of the binned view loop unless the caller picks
+
+// 3 (1 + margin) times a bound on the spectral norm of z J over the clamp
+// box |x/z| <= limx, |y/z| <= limy, where z J = [[fx, 0, -fx x^], [0, fy,
+// -fy y^]]: a primitive's footprint radius obeys r z <= 3 s_max |z J R_v|_2
+// = 3 s_max |z J|_2.  |z J|_2^2 is the larger eigenvalue of
+// [[fx^2 (1 + x^2), fx fy x y], [fx fy x y, fy^2 (1 + y^2)]], which grows
+// with |x^| and |y^|, so its largest value is at a corner of the box.
+__device__ __forceinline__ float footprint_bound(float fx, float fy, float limx, float limy)
+{
+    const float a = fx * fx * (1.0f + limx * limx), c = fy * fy * (1.0f + limy * limy);
+    const float b = fx * fy * limx * limy;
+    const float h = 0.5f * (a - c);
+    return 3.0f * kCullMargin * sqrtf(0.5f * (a + c) + sqrtf(h * h + b * b));
+}
 
 // The records of view slot j (cull may be null: no culling records).
 __device__ __forceinline__ void camera_prep_body(const float* __restrict__ cams, int n_views, int nv, float clamp_k,
@@ -98,11 +112,8 @@ __device__ __forceinline__ void camera_prep_body(const float* __restrict__ cams,
     r.cx1 = ox + lx;
     r.cy0 = oy - ly;
     r.cy1 = oy + ly;
-    {
-        // the culling bound of the footprint in the scaled units of this record
-        const float limx = clamp_k * W / (2.0f * fx), limy = clamp_k * H / (2.0f * fy);
-        r.kvs = sv * (3.0f * kCullMargin * sqrtf(fx * fx * (1.0f + limx * limx) + fy * fy * (1.0f + limy * limy)));
-    }
+    const float kv3 = footprint_bound(fx, fy, clamp_k * W / (2.0f * fx), clamp_k * H / (2.0f * fy));
+    r.kvs = sv * kv3;   // the same bound in the scaled units of this record
 #pragma unroll
     for (int k = 0; k < 13; ++k) r.pad[k] = 0.0f;
     out[j] = r;
@@ -131,8 +142,7 @@ __device__ __forceinline__ void camera_prep_body(const float* __restrict__ cams,
 #pragma unroll
     for (int s = 0; s < 4; ++s)
         q.nn[s] = sqrtf(q.side[s][0] * q.side[s][0] + q.side[s][1] * q.side[s][1] + q.side[s][2] * q.side[s][2]);
-    const float limx = clamp_k * W / (2.0f * fx), limy = clamp_k * H / (2.0f * fy);
-    q.kv3 = 3.0f * kCullMargin * sqrtf(fx * fx * (1.0f + limx * limx) + fy * fy * (1.0f + limy * limy));
+    q.kv3 = kv3;
 #pragma unroll
     for (int k = 0; k < 7; ++k) q.pad[k] = 0.0f;
     cull[j] = q;
