@@ -56,7 +56,10 @@
 // would have added exactly +0 and both paths give bit-identical scores.
 // place_groups orders the groups by how many views they keep (most first,
 // so no long group runs alone at the end), and score_binned gives each wave
-// one group and evaluates its kept views in increasing view order.
+// one group and evaluates its kept views in increasing view order.  For each
+// kept view a wave first computes only its records' camera-space centres and
+// d z, and stops there when no record can pass under the same footprint
+// bound with its own s_max (pair_may_pass): those terms are +0 as well.
 #include <type_traits>
 
 #include "refine_internal.hpp"
