@@ -321,6 +321,53 @@ def test_binned_and_direct_paths_bit_identical(name, n, mode):
     log(f"[paths {name} n={sub.shape[1]} {mode}] identical; nonzero {int((d['scores'] > 0).sum())}")
 
 
+def _edge_scene(n, seed):
+    """Primitives just outside the image of camera() (320 x 240, f = 300),
+    each with 3 s f / z between 0.5 and 1.0 times its distance to the image
+    edge (off-axis Jacobians make the actual radius larger), some
+    needle-like and rotated, plus some at the near plane: about half of
+    them score, so the culling bound and the loop's screen are exercised at
+    the gate's boundary."""
+    from tests.helpers import planes_from_prims, raw_prim
+    rng = np.random.default_rng(seed)
+    prims = []
+    for i in range(n):
+        z = rng.uniform(1.0, 8.0)
+        d = rng.uniform(0.5, 40.0)
+        side = rng.integers(4)
+        u = -d if side == 0 else (320.0 + d if side == 1 else rng.uniform(0.0, 320.0))
+        v = -d if side == 2 else (240.0 + d if side == 3 else rng.uniform(0.0, 240.0))
+        if i % 10 == 0:   # at the near plane
+            z = rng.uniform(0.15, 0.25)
+        x, y = (u - 160.0) * z / 300.0, (v - 120.0) * z / 300.0
+        s = rng.uniform(0.5, 1.0) * d * z / (3.0 * 300.0)
+        ls = np.log(np.full(3, s))
+        q = (1.0, 0.0, 0.0, 0.0)
+        if i % 3 == 0:    # needle-like, rotated
+            ls = ls + np.log(np.array([2.0, 0.3, 0.3]))
+            q = tuple(rng.normal(size=4))
+        prims.append(raw_prim(mu=(x, y, z), log_scale=tuple(ls), quat=q, logit=rng.normal(),
+                              dc=tuple(rng.normal(scale=0.5, size=3))))
+    return planes_from_prims(prims)
+
+
+@pytest.mark.parametrize("mode", [{}, dict(records_per_lane=1), dict(views_per_iteration=2)])
+def test_binned_matches_direct_at_the_gate_boundary(mode):
+    """Binned and direct paths stay bit-identical when many pairs sit at the
+    footprint gate's boundary, where the culling bound and the view loop's
+    screen are tightest."""
+    planes = _edge_scene(12_000, 31)
+    # the reference camera and small shifts of it, so each primitive meets
+    # the boundary at several distances
+    cams = np.stack([camera(t=(dx, dy, 0.0)) for dx, dy in
+                     [(0, 0), (0.01, 0), (-0.01, 0), (0, 0.01), (0, -0.01), (0.02, 0.02)]])
+    d, b = _paths(planes, cams, **mode)
+    np.testing.assert_array_equal(b["scores"].view(np.uint32), d["scores"].view(np.uint32))
+    frac = float((d["scores"] > 0).mean())
+    log(f"[gate boundary {mode}] identical; scored > 0: {frac:.3f}")
+    assert 0.2 < frac < 0.95   # the scene straddles the boundary
+
+
 @pytest.mark.parametrize("rec,vpi", [(1, 1), (2, 1), (2, 2)])
 @pytest.mark.parametrize("n,v", [(5, 3), (777, 1), (9000, 65), (9000, 640)])
 def test_binned_view_masks_and_chunks(n, v, rec, vpi):
