@@ -766,7 +766,9 @@ __global__ __launch_bounds__(kCullThreads) void cull_groups(const GroupBound* __
     // a non-finite bound (non-finite input) disables culling for the group
     const bool no_cull = !(g.rm < INFINITY) || !(g.sg < INFINITY) || !(ca < INFINITY);
     const int nwords = (nv + 63) / 64;
-    CullPiece* const row = reinterpret_cast<CullPiece*>(mask + (size_t)G * nwords);   // little-endian pieces
+    // little-endian pieces of the group's mask row (lanes past the last group
+    // compute but never store)
+    CullPiece* const row = reinterpret_cast<CullPiece*>(mask + (size_t)(live ? G : 0) * nwords);
     uint32_t cnt = 0;
     for (int r = wave; r < (64 / kCullRun) * nwords; r += kCullWaves) {
         const int v0 = r * kCullRun;
