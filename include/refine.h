@@ -115,6 +115,13 @@ typedef struct {
  *           choice, 1 or 2 views evaluated per iteration of the view loop (two
  *           independent evaluations interleaved; each primitive's sum still
  *           adds the views in increasing order)
+ *  score_kind
+ *           REFINE_SCORE_IMPORTANCE (0): the importance score of Eq. 7 with
+ *           the Hessian weights of Eq. 20 (every switch above applies);
+ *           REFINE_SCORE_OPACITY (1): the parameter-space "Opacity" ranking the
+ *           introduction (Sec. 1) contrasts REFINE with, D_i = alpha_i =
+ *           sigmoid(opacity logit); cameras, statistics and the other switches
+ *           are then not used (refine_score still validates its arguments)
  */
 typedef struct {
     double eta;
@@ -130,9 +137,11 @@ typedef struct {
     int32_t score_path;
     int32_t records_per_lane;
     int32_t views_per_iteration;
+    int32_t score_kind;
 } refine_params;
 
 typedef enum { REFINE_PATH_AUTO = 0, REFINE_PATH_DIRECT = 1, REFINE_PATH_BINNED = 2 } refine_score_path;
+typedef enum { REFINE_SCORE_IMPORTANCE = 0, REFINE_SCORE_OPACITY = 1 } refine_score_kind;
 
 /*
  * Scene statistics written to device memory by refine_stats:

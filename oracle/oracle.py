@@ -39,7 +39,7 @@ class _CParams(ctypes.Structure):
                 ("e_col", ctypes.c_double), ("e_opa", ctypes.c_double), ("e_lngem", ctypes.c_double),
                 ("proj_mode", ctypes.c_int32), ("vis_mode", ctypes.c_int32),
                 ("equal_lambda", ctypes.c_int32), ("n_sub_views", ctypes.c_int32),
-                ("amb_eps", ctypes.c_double)]
+                ("amb_k", ctypes.c_double), ("score_kind", ctypes.c_int32)]
 
 
 @dataclasses.dataclass
@@ -54,7 +54,11 @@ class Params:
     covariance energy / Eq. (17) depth term / no projection term.
     vis_mode 0/1: V = alpha / V = 1.  equal_lambda: lambda^k = 1/3.
     n_sub_views: 0 = every view, m = views floor(j V / m).
-    amb_eps: relative width of the band flagged as gate-ambiguous.
+    amb_k: width of the FP32-reach bands of the gate decisions, in units of
+    the FP32 roundoff 2^-24 times each decision's error magnitude (the
+    bounds are derived in refine_oracle.c, above pair_eval).
+    score_kind: 0 = importance score (Eq. 7 with Eq. 20), 1 = the opacity-only
+    ranking of the introduction's parameter-space baseline (D = alpha).
     """
 
     eta: float = 0.05
@@ -67,12 +71,13 @@ class Params:
     vis_mode: int = 0
     equal_lambda: int = 0
     n_sub_views: int = 0
-    amb_eps: float = 1e-5
+    amb_k: float = 16.0
+    score_kind: int = 0
 
     def c(self) -> _CParams:
         return _CParams(self.eta, self.z_near, self.clamp_k, self.e_col, self.e_opa, self.e_lngem,
                         self.proj_mode, self.vis_mode, self.equal_lambda, self.n_sub_views,
-                        self.amb_eps)
+                        self.amb_k, self.score_kind)
 
 
 def load():
@@ -158,13 +163,14 @@ def pair(prim14, cam18, prm: Params | None = None):
     prm = prm or Params()
     p = np.ascontiguousarray(prim14, dtype=np.float32).reshape(14)
     c = np.ascontiguousarray(cam18, dtype=np.float32).reshape(18)
-    out = np.zeros(16, dtype=np.float64)
+    out = np.zeros(20, dtype=np.float64)
     amb = np.zeros(1, dtype=np.int32)
     cp = prm.c()
     g = load().oracle_pair(_ptr(p), _ptr(c), ctypes.byref(cp), _ptr(out), _ptr(amb))
     d = {"x": out[0], "y": out[1], "z": out[2], "u": out[3], "v": out[4],
          "J": out[5:11].reshape(2, 3).copy(), "a": out[11], "b": out[12], "c": out[13],
-         "r": out[14], "P": out[15]}
+         "r": out[14], "P": out[15], "m": out[16], "band_x": out[17], "band_y": out[18],
+         "band_z": out[19]}
     return int(g), int(amb[0]), d
 
 

@@ -38,6 +38,7 @@
 
 #define NPL 59
 #define NCAM 18
+#define NOUT 20   /* doubles written by one pair evaluation */
 
 /* SH band-0 constant 1/(2 sqrt(pi)): converts a DC coefficient to colour. */
 static const double SH_C0 = 0.28209479177387814;
@@ -53,8 +54,13 @@ typedef struct {
     int32_t vis_mode;  /* 0: V = alpha (Eq. 12, T = 1), 1: V = 1 */
     int32_t equal_lambda; /* 1: lambda^k = 1/3 ("Equal lambda" of Table 3) */
     int32_t n_sub_views;  /* 0: all views; m > 0: views floor(j V / m), j < m */
-    double amb_eps;    /* width of the FP32-reach band used to flag gate-ambiguous pairs */
+    double amb_k;      /* FP32-reach band of the gate decisions, in units of the FP32
+                          roundoff 2^-24 times the error magnitudes below */
+    int32_t score_kind;   /* 0: importance of Eq. (7) with Eq. (20); 1: opacity alone (Sec. 1) */
 } oracle_params;
+
+/* Unit roundoff of IEEE single precision (round to nearest). */
+static const double FP32_U = 5.9604644775390625e-08;
 
 /* Number of threads the OpenMP loops use (1 without OpenMP). */
 int oracle_num_threads(void)
@@ -80,6 +86,8 @@ typedef struct {
     double Rq[3][3];
     double Sigma[3][3];   /* 3D covariance Rq diag(s^2) Rq^T */
     double sbar2;         /* mean squared scale (s0^2 + s1^2 + s2^2) / 3 */
+    double smax;          /* largest scale */
+    double lsmax;         /* largest |log-scale| (the error of an FP32 exp grows with it) */
     double alpha;
     double rgb[3];        /* DC colour 0.5 + C0 * dc */
     double Y;             /* perceptual luma (BT.601 weights) */
@@ -103,7 +111,14 @@ static void quat_to_rot(double w, double x, double y, double z, double R[3][3])
 static void activate(const float* planes, int64_t stride, int64_t i, prim_t* p)
 {
     for (int k = 0; k < 3; ++k) p->mu[k] = plane(planes, stride, 0 + k, i);
-    for (int k = 0; k < 3; ++k) p->s[k] = exp(plane(planes, stride, 3 + k, i));
+    p->lsmax = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        double ls = plane(planes, stride, 3 + k, i);
+        p->s[k] = exp(ls);
+        if (fabs(ls) > p->lsmax) p->lsmax = fabs(ls);
+    }
+    p->smax = p->s[0];
+    for (int k = 1; k < 3; ++k) if (p->s[k] > p->smax) p->smax = p->s[k];
     quat_to_rot(plane(planes, stride, 6, i), plane(planes, stride, 7, i),
                 plane(planes, stride, 8, i), plane(planes, stride, 9, i), p->Rq);
     for (int r = 0; r < 3; ++r)
@@ -184,19 +199,46 @@ void oracle_lambda(const double F[4], const oracle_params* prm, double lam[3])
 
 /* ------------------------------------------------------- per-view terms */
 
-/* One (primitive, view) evaluation.  out (16 doubles):
+/* One (primitive, view) evaluation.  out (NOUT doubles):
  *  0..2  x, y, z   camera-space centre
  *  3..4  u, v      projected centre, Eq. (13)
  *  5..10 J         2x3 EWA Jacobian of the projection (clamped), row-major, Eq. (14)
  *  11..13 a, b, c  projected 2D covariance Sigma' = J W Sigma W^T J^T
  *  14    r         footprint radius 3 sqrt(lambda_max(Sigma'))
  *  15    P         projection term of the selected mode (Eq. 14-17 reading)
+ *  16    m         signed footprint margin min(u + r, W - u + r, v + r, H - v + r)
+ *  17, 18          FP32-reach bands of the left/right and top/bottom edge margins
+ *  19              FP32-reach band of the depth z
  * returns the gate g (1 visible, 0 not) and writes ambiguity into *amb:
  * bit 0 = near-plane decision within FP32 reach, bit 1 = footprint decision
  * within FP32 reach; *could = 1 when an evaluation perturbed within that
- * reach could find the pair visible.  When z <= 0 only x, y, z are written. */
+ * reach could find the pair visible.  When z <= 0 only x, y, z are written.
+ *
+ * FP32 reach.  The gate is discontinuous, so an FP32 evaluation of the same
+ * formulas (any operation order, fused or not, approximate reciprocals) can
+ * take the other decision when a margin is within its rounding error.  With
+ * u = 2^-24 and K = amb_k, the bands bound that error to first order:
+ *  depth:   z = R_2 . mu + t_z is a 3-term dot product of FP32 values, so its
+ *           error is a few u times mag_z = |R_2| . |mu| + |t_z|:
+ *           band_z = K u (mag_z + z_near).
+ *  centre:  u_px = fx x / z + cx carries the errors of x and z (u mag_x,
+ *           u mag_z), of the division and of the offsets:
+ *           E_x = (fx mag_x + (|cx| + W + |u_px - cx|) mag_z) / z + |u_px| + W,
+ *           and E_y likewise (these also bound forms that premultiply the
+ *           rows by intrinsics or shift the origin to the image centre).
+ *  radius:  r = sigma_max(3 J W L) with L = R(q) diag(s) (Sigma = L L^T), and
+ *           sigma_max moves by at most the spectral norm of the error of its
+ *           argument.  J's entries carry the relative error of 1/z (u mag_z / z)
+ *           and the centre errors through x/z and y/z (E_x / z, E_y / z); L's
+ *           entries the error of an FP32 exp, which grows with |log-scale|;
+ *           forming lambda_max from the 2x2 sums costs a few u of r:
+ *           E_r = r + 3 s_max ((1 + mag_z / z + max|log-scale|) |J|_F
+ *                               + (E_x + E_y) / z).
+ *  Each edge margin (u_px + r, W - u_px + r, ...) then has the band
+ *  K u (E_x + E_r) or K u (E_y + E_r), and the footprint decision is
+ *  ambiguous when the smallest margin could reach either sign within them. */
 static int pair_eval(const prim_t* p, const float* cam, const oracle_params* prm,
-                     double out[16], int* amb, int* could)
+                     double out[NOUT], int* amb, int* could)
 {
     double Rv[3][3], t[3];
     for (int r = 0; r < 3; ++r) for (int c = 0; c < 3; ++c) Rv[r][c] = (double)cam[3 * r + c];
@@ -210,11 +252,13 @@ static int pair_eval(const prim_t* p, const float* cam, const oracle_params* prm
     }
     double x = pc[0], y = pc[1], z = pc[2];
     out[0] = x; out[1] = y; out[2] = z;
-    for (int k = 3; k < 16; ++k) out[k] = 0.0;
+    for (int k = 3; k < NOUT; ++k) out[k] = 0.0;
     *amb = 0;
     *could = 0;
 
-    double tz = prm->amb_eps * (mag[2] + prm->z_near);
+    double ku = prm->amb_k * FP32_U;
+    double tz = ku * (mag[2] + prm->z_near);
+    out[19] = tz;
     int near_ok = z > prm->z_near;
     if (fabs(z - prm->z_near) <= tz) *amb |= 1;
     if (z <= 0.0) { *amb = 0; return 0; }
@@ -244,15 +288,25 @@ static int pair_eval(const prim_t* p, const float* cam, const oracle_params* prm
     double half = 0.5 * (a - c);
     double lmax = 0.5 * (a + c) + sqrt(half * half + b * b);
     double r = 3.0 * sqrt(lmax);
-    double m = u + r;
-    if (W - u + r < m) m = W - u + r;
-    if (v + r < m) m = v + r;
-    if (H - v + r < m) m = H - v + r;
+    double edge[4] = {u + r, W - u + r, v + r, H - v + r};
+    double m = edge[0];
+    for (int e = 1; e < 4; ++e) if (edge[e] < m) m = edge[e];
     int foot_ok = m > 0.0;
-    double tm = prm->amb_eps * (fabs(u - cx) + fabs(v - cy) + r + W + H +
-                                (fx + fy) * (mag[0] + mag[1] + mag[2]) *
-                                    (1.0 + fabs(x / z) + fabs(y / z)) / z);
-    if (fabs(m) <= tm) *amb |= 2;
+    /* FP32 reach of each edge margin (see above) */
+    double Ex = (fx * mag[0] + (fabs(cx) + W + fabs(u - cx)) * mag[2]) / z + fabs(u) + W;
+    double Ey = (fy * mag[1] + (fabs(cy) + H + fabs(v - cy)) * mag[2]) / z + fabs(v) + H;
+    double Jf = sqrt(J[0][0] * J[0][0] + J[0][2] * J[0][2] + J[1][1] * J[1][1] + J[1][2] * J[1][2]);
+    double Er = r + 3.0 * p->smax * ((1.0 + mag[2] / z + p->lsmax) * Jf + (Ex + Ey) / z);
+    double band[4] = {ku * (Ex + Er), ku * (Ex + Er), ku * (Ey + Er), ku * (Ey + Er)};
+    double mlo = edge[0] - band[0], mhi = edge[0] + band[0];
+    for (int e = 1; e < 4; ++e) {
+        if (edge[e] - band[e] < mlo) mlo = edge[e] - band[e];
+        if (edge[e] + band[e] < mhi) mhi = edge[e] + band[e];
+    }
+    if (mlo <= 0.0 && mhi >= 0.0) *amb |= 2;
+    out[16] = m;
+    out[17] = band[0];
+    out[18] = band[2];
 
     double P;
     if (prm->proj_mode == 0)
@@ -273,7 +327,7 @@ static int pair_eval(const prim_t* p, const float* cam, const oracle_params* prm
 /* Exposed for the tests: evaluate one pair from raw (unactivated) values.
  * prim14 = {x,y,z, ls0,ls1,ls2, qw,qx,qy,qz, logit, dc_r,dc_g,dc_b}. */
 int oracle_pair(const float* prim14, const float* cam, const oracle_params* prm,
-                double out[16], int32_t* amb)
+                double out[NOUT], int32_t* amb)
 {
     prim_t p;
     activate(prim14, 1, 0, &p);
@@ -299,7 +353,9 @@ void oracle_activate(const float* prim14, double out[18])
 /* Importance scores (Eq. 20 then Eq. 7) of primitives idx[0..m) (all n when
  * idx is NULL, m = n).  lam = {gem, col, opa}.  D[j] is the score of primitive
  * idx[j]; Dlo/Dhi (nullable) bound it when gate-ambiguous pairs are excluded /
- * included; namb (nullable) counts the ambiguous pairs. */
+ * included; namb (nullable) counts the ambiguous pairs.
+ * With score_kind = 1 the score is the parameter-space opacity ranking the
+ * introduction (Sec. 1) sets REFINE against: D = alpha, no views. */
 void oracle_score(const float* planes, int64_t n, int64_t stride, const float* cams, int32_t n_views,
                   const oracle_params* prm, const double lam[3], const int64_t* idx, int64_t m,
                   double* D, double* Dlo, double* Dhi, int32_t* namb)
@@ -312,11 +368,18 @@ void oracle_score(const float* planes, int64_t n, int64_t stride, const float* c
         int64_t i = idx ? idx[j] : j;
         prim_t p;
         activate(planes, stride, i, &p);
+        if (prm->score_kind == 1) {
+            D[j] = p.alpha;
+            if (Dlo) Dlo[j] = p.alpha;
+            if (Dhi) Dhi[j] = p.alpha;
+            if (namb) namb[j] = 0;
+            continue;
+        }
         double S = 0.0, Slo = 0.0, Shi = 0.0;
         int32_t na = 0;
         for (int32_t jv = 0; jv < nv; ++jv) {
             int64_t v = (nv == n_views) ? jv : ((int64_t)jv * n_views) / nv;
-            double o[16];
+            double o[NOUT];
             int amb = 0, could = 0;
             int g = pair_eval(&p, cams + v * NCAM, prm, o, &amb, &could);
             double P = o[15];

@@ -22,6 +22,7 @@ REFINE_F32, REFINE_BF16, REFINE_F16 = 0, 1, 2
 PROJ_COV, PROJ_DEPTH, PROJ_NONE = 0, 1, 2
 VIS_ALPHA, VIS_NONE = 0, 1
 PATH_AUTO, PATH_DIRECT, PATH_BINNED = 0, 1, 2
+SCORE_IMPORTANCE, SCORE_OPACITY = 0, 1
 
 EXPORTED = ("refine_version", "refine_status_string", "refine_params_default", "refine_prune_count",
             "refine_workspace_size", "refine_stats", "refine_score", "refine_score_prepare", "refine_score_cameras",
@@ -40,7 +41,7 @@ class Params(ctypes.Structure):
                 ("proj_mode", ctypes.c_int32), ("vis_mode", ctypes.c_int32),
                 ("equal_lambda", ctypes.c_int32), ("n_sub_views", ctypes.c_int32),
                 ("score_path", ctypes.c_int32), ("records_per_lane", ctypes.c_int32),
-                ("views_per_iteration", ctypes.c_int32)]
+                ("views_per_iteration", ctypes.c_int32), ("score_kind", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):

@@ -57,6 +57,7 @@ refine_status check_params(const refine_params* p)
     if (p->score_path < REFINE_PATH_AUTO || p->score_path > REFINE_PATH_BINNED) return REFINE_E_INVALID;
     if (p->records_per_lane < 0 || p->records_per_lane > 2) return REFINE_E_INVALID;
     if (p->views_per_iteration < 0 || p->views_per_iteration > 2) return REFINE_E_INVALID;
+    if (p->score_kind != REFINE_SCORE_IMPORTANCE && p->score_kind != REFINE_SCORE_OPACITY) return REFINE_E_INVALID;
     return REFINE_OK;
 }
 
@@ -214,6 +215,7 @@ void refine_params_default(refine_params* p)
     p->vis_mode = REFINE_VIS_ALPHA;
     p->equal_lambda = 0;
     p->n_sub_views = 0;
+    p->score_kind = REFINE_SCORE_IMPORTANCE;
 }
 
 int64_t refine_prune_count(int64_t n, double ratio)

@@ -327,6 +327,22 @@ __global__ __launch_bounds__(kBlock) void score_direct(const void* __restrict__ 
                                 blockIdx.x * kBlock + threadIdx.x);
 }
 
+// The opacity-only ranking (score_kind = OPACITY): D_i = alpha_i, the same
+// FP32 sigmoid the activation computes.
+template <int ST>
+__device__ __forceinline__ void score_opacity_body(const void* __restrict__ planes, int64_t stride, int n,
+                                                   float* __restrict__ out, int i)
+{
+    if (i < n) out[i] = 1.0f / (1.0f + __expf(-load_plane<ST>(planes, stride, 10, i)));
+}
+
+template <int ST>
+__global__ __launch_bounds__(kBlock) void score_opacity(const void* __restrict__ planes, int64_t stride, int n,
+                                                          float* __restrict__ out)
+{
+    score_opacity_body<ST>(planes, stride, n, out, blockIdx.x * kBlock + threadIdx.x);
+}
+
 // Grouped launches: the camera records of one job per block, and the direct
 // view loop over 256 primitives of one job per block.
 __global__ __launch_bounds__(kBlock) void camera_prep_batch(const BatchJob* __restrict__ jobs, float clamp_k)
@@ -334,6 +350,16 @@ __global__ __launch_bounds__(kBlock) void camera_prep_batch(const BatchJob* __re
     const BatchJob& b = jobs[blockIdx.x];
     for (int j = threadIdx.x; j < b.nv; j += kBlock)
         camera_prep_body(b.cams, b.n_views, b.nv, clamp_k, b.cam_rec, nullptr, j);
+}
+
+__global__ __launch_bounds__(kBlock) void score_opacity_batch(const BatchJob* __restrict__ jobs, int nj)
+{
+    const BatchJob& b = jobs[batch_job_of<false>(jobs, nj, blockIdx.x)];
+    const int i = ((int)blockIdx.x - b.block0) * kBlock + (int)threadIdx.x;
+    if (b.st == kStoreF32)
+        score_opacity_body<kStoreF32>(b.planes, b.stride, b.n, b.scores, i);
+    else
+        score_opacity_body<kStoreBF16F16>(b.planes, b.stride, b.n, b.scores, i);
 }
 
 template <int PROJ>
@@ -1025,6 +1051,7 @@ void views_mode(const void* planes, int64_t stride, int n, const refine_params& 
 
 bool binned_path(const refine_params& prm, int64_t n)
 {
+    if (prm.score_kind == REFINE_SCORE_OPACITY) return false;   // no pairs to schedule
     return prm.score_path == REFINE_PATH_BINNED || (prm.score_path == REFINE_PATH_AUTO && n >= kBinnedMinPrims);
 }
 
@@ -1051,6 +1078,7 @@ hipError_t launch_score_prepare(const void* planes, int st, int64_t stride, int6
                                 int32_t n_views, const refine_params& prm, const refine_stats_t* d_stats,
                                 const Workspace& ws, hipStream_t stream)
 {
+    if (prm.score_kind == REFINE_SCORE_OPACITY) return hipSuccess;   // nothing depends on the cameras
     const int nv = views_of(prm, n_views);
     const bool binned = n > 0 && binned_path(prm, n);
     const int threads = binned ? (nv > kCells * kBinCopies ? nv : kCells * kBinCopies) : nv;
@@ -1068,6 +1096,10 @@ hipError_t launch_score_batch(const BatchJob* d_jobs, int n_jobs, int total_bloc
 {
     const int vis = prm.vis_mode == REFINE_VIS_ALPHA ? 1 : 0;
     const float eta = (float)prm.eta, zn = (float)prm.z_near;
+    if (prm.score_kind == REFINE_SCORE_OPACITY) {
+        hipLaunchKernelGGL(score_opacity_batch, dim3(total_blocks), dim3(kBlock), 0, stream, d_jobs, n_jobs);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(camera_prep_batch, dim3(n_jobs), dim3(kBlock), 0, stream, d_jobs, (float)prm.clamp_k);
     switch (prm.proj_mode) {
     case REFINE_PROJ_COV:
@@ -1104,6 +1136,20 @@ hipError_t launch_score_views(const void* planes, int st, int64_t stride, int64_
     unsigned long long* counter = (d_evaluated && binned) ? ws.evaluated : nullptr;
     if (binned && n == 0 && counter)   // the view loop, which clears the pair counters, does not run
         hipLaunchKernelGGL(views_init, dim3(1), dim3(2 * kEvalSlots), 0, stream, counter);
+    if (prm.score_kind == REFINE_SCORE_OPACITY) {
+        if (n > 0) {
+            const dim3 grid((unsigned)((n + kBlock - 1) / kBlock));
+            if (st == kStoreF32)
+                hipLaunchKernelGGL(score_opacity<kStoreF32>, grid, dim3(kBlock), 0, stream, planes, stride, (int)n,
+                                   d_scores);
+            else
+                hipLaunchKernelGGL(score_opacity<kStoreBF16F16>, grid, dim3(kBlock), 0, stream, planes, stride,
+                                   (int)n, d_scores);
+        }
+        if (d_evaluated)   // no pairs are evaluated
+            hipLaunchKernelGGL(counter_store, dim3(1), dim3(1), 0, stream, ws.evaluated, d_evaluated, (int64_t)0);
+        return hipGetLastError();
+    }
     if (n > 0)
         dispatch_mode(prm.proj_mode, st, [&](auto proj_c, auto st_c) {
             views_mode<decltype(proj_c)::value, decltype(st_c)::value>(planes, stride, (int)n, prm, d_stats, d_scores,

@@ -85,7 +85,8 @@ def test_batch_matches_single_scene_calls():
         check_scores(j["scores"].cpu().numpy(), D, lo, hi, what)
 
 
-@pytest.mark.parametrize("mode", [dict(proj_mode=1), dict(proj_mode=2, vis_mode=1), dict(n_sub_views=5, equal_lambda=1)])
+@pytest.mark.parametrize("mode", [dict(proj_mode=1), dict(proj_mode=2, vis_mode=1), dict(n_sub_views=5, equal_lambda=1),
+                                  dict(score_kind=1)])
 def test_batch_method_switches(mode):
     """The batch applies the shared parameters like the single calls do."""
     import torch

@@ -29,17 +29,21 @@ def _mixed(planes):
     return q, synth.dequantize_bf16_f16(q)
 
 
-def _pipeline(q, deq, cams, n, ratio, what):
+def _pipeline(q, deq, cams, n, ratios, what):
+    """Stats, scores, then for each ratio the mask and compaction, all
+    against the oracle on the dequantised scene; returns the last run."""
     import oracle
     F, lam, D, lo, hi = oracle_all(deq, cams, n=n)
-    n_prune = oracle.n_prune(n, ratio)
-    r = run_gpu(q, cams, n=n, ratio=ratio)
-    check_stats(r["stats"], F, lam, what)
-    assert r["stats"]["n"] == n and r["stats"]["n_nonfinite"] == 0
-    check_scores(r["scores"], D, lo, hi, f"{what} scores")
-    np.testing.assert_array_equal(r["keep"], expected_keep_from_scores(r["scores"], n_prune))
-    check_mask_vs_oracle(r["keep"], D, lo, hi, n_prune, f"{what} mask")
-    check_compact(q, n, r)
+    r = None
+    for ratio in np.atleast_1d(ratios):
+        n_prune = oracle.n_prune(n, float(ratio))
+        r = run_gpu(q, cams, n=n, ratio=float(ratio))
+        check_stats(r["stats"], F, lam, what)
+        assert r["stats"]["n"] == n and r["stats"]["n_nonfinite"] == 0
+        check_scores(r["scores"], D, lo, hi, f"{what} scores")
+        np.testing.assert_array_equal(r["keep"], expected_keep_from_scores(r["scores"], n_prune))
+        check_mask_vs_oracle(r["keep"], D, lo, hi, n_prune, f"{what} mask beta={float(ratio)}")
+        check_compact(q, n, r)
     return r
 
 
@@ -103,7 +107,7 @@ def test_medium_mixed_parity_and_storage_effect():
     planes, cams, spec = workload("medium")
     q, deq = _mixed(planes)
     log(f"medium mixed: n={spec.n} V={cams.shape[0]}")
-    r16 = _pipeline(q, deq, cams, spec.n, 0.5, "medium mixed")
+    r16 = _pipeline(q, deq, cams, spec.n, (0.9, 0.5), "medium mixed")
     r32 = run_gpu(planes, cams)
     s16, s32 = r16["scores"].astype(np.float64), r32["scores"].astype(np.float64)
     nz = s32 > 0

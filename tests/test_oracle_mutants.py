@@ -33,7 +33,7 @@ MUTANTS = [
     ("eta dropped from anisotropy", "sumGem += smax / (smin + eta);", "sumGem += smax / smin;"),
     ("eta dropped from lambda~gem", "log(F[3] + prm->eta)", "log(F[3])"),
     ("2-sigma footprint", "double r = 3.0 * sqrt(lmax);", "double r = 2.0 * sqrt(lmax);"),
-    ("bottom edge tested against W", "if (H - v + r < m) m = H - v + r;", "if (W - v + r < m) m = W - v + r;"),
+    ("bottom edge tested against W", "v + r, H - v + r};", "v + r, W - v + r};"),
     ("near plane ignored", "int near_ok = z > prm->z_near;", "int near_ok = 1;"),
     ("sum instead of mean over views", "d += lam[k] * (S / nv) * gt[k];", "d += lam[k] * S * gt[k];"),
     ("mean squared scale from one axis",
@@ -48,6 +48,14 @@ MUTANTS = [
     ("no Jacobian clamp", "double xh = clampd(x / z, -limx, limx);", "double xh = x / z;"),
     ("principal point dropped", "double u = fx * x / z + cx;", "double u = fx * x / z;"),
     ("subsampling picks the first views", "((int64_t)jv * n_views) / nv", "jv"),
+    ("FP32-reach band 100x wider", "double ku = prm->amb_k * FP32_U;", "double ku = 100.0 * prm->amb_k * FP32_U;"),
+    ("centre error left out of the band", "ku * (Ex + Er), ku * (Ex + Er), ku * (Ey + Er), ku * (Ey + Er)",
+     "ku * Er, ku * Er, ku * Er, ku * Er"),
+    ("depth band without the depth's magnitude", "double tz = ku * (mag[2] + prm->z_near);",
+     "double tz = ku * prm->z_near;"),
+    ("opacity ranking by the raw logit", "D[j] = p.alpha;", "D[j] = plane(planes, stride, 10, i);"),
+    ("footprint flag on the larger margin", "if (edge[e] - band[e] < mlo) mlo = edge[e] - band[e];",
+     "if (edge[e] - band[e] > mlo) mlo = edge[e] - band[e];"),
 ]
 
 
@@ -68,6 +76,7 @@ def test_planted_mistake_is_caught(tmp_path, name, before, after):
     r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
                         "-m", "not gpu", "tests/test_oracle_activation_stats.py",
                         "tests/test_oracle_projection_score.py", "tests/test_oracle_renderer.py",
+                        "tests/test_oracle_gate_band.py",
                         "tests/test_oracle_select_compact.py"],
                        cwd=dst, capture_output=True, text=True, timeout=300)
     assert r.returncode != 0, f"no pin caught the planted mistake: {name}\n{r.stdout[-2000:]}"

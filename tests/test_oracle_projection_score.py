@@ -268,3 +268,35 @@ def test_ablation_switches(oracle_lib):
     D1 = oracle_lib.score(pl, cams, LAM, P(proj_mode=2))[0]
     Dd = oracle_lib.score(pl, cams, LAM, P(proj_mode=1))[0]
     assert np.all((D1 > 0) == (D > 0)) and np.all((Dd > 0) == (D > 0))
+
+
+def test_opacity_only_ranking(oracle_lib):
+    """The parameter-space "Opacity" ranking (Sec. 1): D = alpha =
+    sigmoid(logit).  Pinned by the logistic function's symmetry
+    D(x) + D(-x) = 1 and D(0) = 1/2, by its ranking being a stable sort of
+    the raw logits (sigmoid is strictly increasing), by its independence of
+    every other attribute and of the cameras, and by exact (interval-free)
+    values."""
+    pl, cams = _scene(500)
+    n = pl.shape[1]
+    pl[10, :5] = 0.0
+    pl[10, 5:9] = pl[10, 9]                     # ties: equal logits rank by index
+    prm = P(score_kind=1)
+    D, lo, hi, na = oracle_lib.score(pl, cams, LAM, prm)
+    assert np.all(D[:5] == 0.5)
+    neg = pl.copy()
+    neg[10] = -pl[10]
+    Dn = oracle_lib.score(neg, cams, LAM, prm)[0]
+    np.testing.assert_allclose(D + Dn, 1.0, rtol=0, atol=4e-16)
+    assert np.all((D > 0) & (D < 1))
+    np.testing.assert_array_equal(lo, D)
+    np.testing.assert_array_equal(hi, D)
+    assert np.all(na == 0)
+    for k in (1, n // 3, n - 1):
+        keep, order = oracle_lib.select(D, k)
+        np.testing.assert_array_equal(order, np.lexsort((np.arange(n), pl[10].astype(np.float64))))
+    other = pl.copy()
+    rng = np.random.default_rng(8)
+    other[0:10] = rng.normal(size=(10, n)).astype(np.float32)
+    other[11:] = rng.normal(size=(48, n)).astype(np.float32)
+    np.testing.assert_array_equal(oracle_lib.score(other, cams[:3], LAM, prm)[0], D)
