@@ -197,6 +197,26 @@ refine_status refine_stats(const refine_scene* scene, const refine_params* param
                            refine_stats_t* d_stats, void* d_ws, size_t ws_bytes, void* stream);
 
 /*
+ * refine_stats without a workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation).  The same kernels and results as refine_stats, bit for
+ * bit; the tile partials live in a fixed 1 MiB array in device memory that
+ * the library holds on every GPU it runs on until the process ends.
+ *  - n <= REFINE_STATS_NOALLOC_MAX_N, else REFINE_E_UNSUPPORTED (nothing is
+ *    enqueued); other arguments and errors as for refine_stats.
+ *  - The work runs on the CURRENT device's array (stream must belong to the
+ *    current device).  The first call on a device resolves the array's
+ *    address there (no allocation); that call is best made before any graph
+ *    capture starts.
+ *  - Every call on one GPU shares that GPU's array: calls that overlap on one
+ *    GPU (concurrent streams, or threads) race and give wrong statistics;
+ *    order them on one stream.  Nothing needs clearing between calls.
+ */
+#define REFINE_STATS_NOALLOC_MAX_N 67108864
+refine_status refine_stats_noalloc(const refine_scene* scene, const refine_params* params, refine_stats_t* d_stats,
+                                   void* stream);
+
+/*
  * Importance scores D_i (Eq. 7 with the Hessian weights of Eq. 20):
  *   D_i = sum_k lambda^k G~_i^k * (1/|V|) sum_v g_i^v V_i P_i^v
  * with the visibility V_i and projection P_i^v of the selected modes and the

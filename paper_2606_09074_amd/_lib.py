@@ -27,7 +27,9 @@ SCORE_IMPORTANCE, SCORE_OPACITY = 0, 1
 EXPORTED = ("refine_version", "refine_status_string", "refine_params_default", "refine_prune_count",
             "refine_workspace_size", "refine_stats", "refine_score", "refine_score_prepare", "refine_score_cameras",
             "refine_score_views",
-            "refine_select", "refine_compact", "refine_prune_batch_workspace_size", "refine_prune_batch")
+            "refine_select", "refine_compact", "refine_prune_batch_workspace_size", "refine_prune_batch",
+            "refine_stats_noalloc")
+STATS_NOALLOC_MAX_N = 67108864
 
 
 class Scene(ctypes.Structure):
@@ -97,6 +99,8 @@ def load():
     lib.refine_workspace_size.restype = i32
     lib.refine_stats.argtypes = [ctypes.POINTER(Scene), ctypes.POINTER(Params), P, P, sz, P]
     lib.refine_stats.restype = i32
+    lib.refine_stats_noalloc.argtypes = [ctypes.POINTER(Scene), ctypes.POINTER(Params), P, P]
+    lib.refine_stats_noalloc.restype = i32
     lib.refine_score.argtypes = [ctypes.POINTER(Scene), P, i32, ctypes.POINTER(Params), P, P, P, sz, P]
     lib.refine_score.restype = i32
     lib.refine_score_prepare.argtypes = [ctypes.POINTER(Scene), P, i32, ctypes.POINTER(Params), P, P, sz, P]

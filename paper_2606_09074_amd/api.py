@@ -19,6 +19,7 @@ from . import _lib
 from ._lib import Params, Scene, Stats, check, default_params
 
 __all__ = ["Params", "default_params", "workspace", "workspace_size", "prune_count", "refine_stats",
+           "refine_stats_noalloc",
            "refine_score", "refine_score_prepare", "refine_score_cameras", "refine_score_views", "refine_select",
            "refine_compact",
            "refine_prune_batch", "stats_from_tensor", "prune", "prune_batch", "version"]
@@ -87,6 +88,19 @@ def refine_stats(planes: torch.Tensor, stats_out: torch.Tensor, ws: torch.Tensor
         raise ValueError("stats_out too small or not on the GPU")
     check(_lib.load().refine_stats(ctypes.byref(sc), ctypes.byref(params), _ptr(stats_out), _ptr(ws),
                                    ws.numel(), _stream_ptr(stream)), "refine_stats")
+
+
+def refine_stats_noalloc(planes: torch.Tensor, stats_out: torch.Tensor, params: Optional[Params] = None,
+                         n: Optional[int] = None, stream=None) -> None:
+    """refine_stats on the library's fixed device array instead of a
+    workspace (n <= _lib.STATS_NOALLOC_MAX_N; calls on one GPU must not
+    overlap)."""
+    params = params or default_params()
+    sc = _scene(planes, n)
+    if stats_out.numel() * stats_out.element_size() < _lib.STATS_BYTES or not stats_out.is_cuda:
+        raise ValueError("stats_out too small or not on the GPU")
+    check(_lib.load().refine_stats_noalloc(ctypes.byref(sc), ctypes.byref(params), _ptr(stats_out),
+                                           _stream_ptr(stream)), "refine_stats_noalloc")
 
 
 def refine_score(planes: torch.Tensor, cams: torch.Tensor, stats: torch.Tensor, scores_out: torch.Tensor,

@@ -249,6 +249,23 @@ refine_status refine_stats(const refine_scene* scene, const refine_params* param
     return e == hipSuccess ? REFINE_OK : REFINE_E_HIP;
 }
 
+refine_status refine_stats_noalloc(const refine_scene* scene, const refine_params* params, refine_stats_t* d_stats,
+                                   void* stream)
+{
+    refine_status s = check_scene(scene);
+    if (s != REFINE_OK) return s;
+    if ((s = check_params(params)) != REFINE_OK) return s;
+    if (!d_stats) return REFINE_E_INVALID;
+    if (scene->n > (int64_t)REFINE_STATS_NOALLOC_MAX_N) return REFINE_E_UNSUPPORTED;
+    double* part = nullptr;
+    if (stats_scratch(&part) != hipSuccess) return REFINE_E_HIP;
+    Workspace ws = {};
+    ws.stat_part = part;   // the only workspace section the statistics kernels use
+    const hipError_t e = launch_stats(scene->planes, storage_of(scene), scene->stride, scene->n, *params, d_stats,
+                                      ws, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? REFINE_OK : REFINE_E_HIP;
+}
+
 namespace {
 
 refine_status check_score_args(const refine_scene* scene, int32_t n_views, const refine_params* params,

@@ -33,6 +33,8 @@ constexpr int kHistCopies = 8;    // selection histogram copies: spreads the ato
 constexpr int kSelectHistWords = 3 * kHistCopies * kHistBins;   // one set of copies per radix pass
 constexpr int kSelectLastBins = 1 << 10;   // digits of the last radix pass (its per-tile rows)
 constexpr int kStatSlots = 8;      // doubles per stats partial
+constexpr int kNoAllocStatTiles = REFINE_STATS_NOALLOC_MAX_N / kTile;   // tiles of refine_stats_noalloc
+static_assert(REFINE_STATS_NOALLOC_MAX_N % kTile == 0, "whole tiles of scratch");
 
 // Prepared camera record (fp32, 128 bytes), built by camera_prep.  Pixel
 // quantities are scaled by sv = 1 / sqrt(fx^2 + fy^2): the gate is invariant
@@ -216,6 +218,10 @@ hipError_t launch_stats(const void* planes, int st, int64_t stride, int64_t n, c
 hipError_t launch_score_prepare(const void* planes, int st, int64_t stride, int64_t n, const float* d_cams,
                                 int32_t n_views, const refine_params& prm, const refine_stats_t* d_stats,
                                 const Workspace& ws, hipStream_t stream);
+// Device address of this device's refine_stats_noalloc scratch (the tile
+// partials of kNoAllocStatTiles tiles), resolved on the first call per device
+// (the current device).
+hipError_t stats_scratch(double** out);
 hipError_t launch_stats_batch(const BatchJob* d_jobs, int n_jobs, int total_tiles, const refine_params& prm,
                               hipStream_t stream);
 hipError_t launch_score_batch(const BatchJob* d_jobs, int n_jobs, int total_blocks, const refine_params& prm,

@@ -17,11 +17,25 @@
 // HBM traffic: 14 planes x 4 B = 56 B per primitive read (the 28 B of the
 // feature planes plus the non-finite check of the rest; half of that for
 // BF16/FP16 storage), 64 B per tile written.
+#include <mutex>
+
 #include "refine_internal.hpp"
 
 namespace refine {
 
+// Tile partials of refine_stats_noalloc, for callers that cannot allocate a
+// workspace: a fixed array in device memory (every GPU the library runs on
+// holds its own copy until the process ends).  Host code never passes the
+// array's name to a kernel (on the host it is only a stand-in for the
+// symbol): it uses the device address hipGetSymbolAddress returns, resolved
+// once per device.
+static __device__ __align__(256) double scratch[(size_t)kNoAllocStatTiles * kStatSlots];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+double* g_scratch_ptr[kMaxDevices] = {};
 
 constexpr float kShC0 = 0.28209479177387814f;   // real SH band-0 basis value 1/(2 sqrt(pi))
 
@@ -329,6 +343,23 @@ hipError_t launch_stats_batch(const BatchJob* d_jobs, int n_jobs, int total_tile
                        (float)prm.eta);
     hipLaunchKernelGGL(stats_finalize_batch, dim3(n_jobs), dim3(kBlock), 0, stream, d_jobs, prm);
     return hipGetLastError();
+}
+
+hipError_t stats_scratch(double** out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
 }
 
 hipError_t launch_stats(const void* planes, int st, int64_t stride, int64_t n, const refine_params& prm,

@@ -245,3 +245,24 @@ def test_batch_validation(lib):
     assert size(job(n=4096 * 4096 + 1))[0] == U
     assert run(job(), wsb=b1 - 1) == W
     assert run(job(), ws=0) == W
+
+
+def test_stats_noalloc_validation(lib):
+    """The allocation-free statistics call validates like refine_stats and
+    rejects scenes beyond its fixed array, all before touching HIP."""
+    from paper_2606_09074_amd import _lib
+    p = _lib.default_params()
+    E, U = _lib.REFINE_E_INVALID, _lib.REFINE_E_UNSUPPORTED
+    call = lambda sc, prm=p, out=FAKE: lib.refine_stats_noalloc(
+        ctypes.byref(sc) if sc is not None else None, ctypes.byref(prm) if prm is not None else None, out, None)
+    assert call(None) == E
+    assert call(_scene(n=-1)) == E
+    assert call(_scene(planes=0)) == E
+    assert call(_scene(), prm=None) == E
+    assert call(_scene(), out=None) == E
+    bad = _lib.default_params()
+    bad.eta = 0.0
+    assert call(_scene(), prm=bad) == E
+    assert _lib.STATS_NOALLOC_MAX_N == 1 << 26
+    assert call(_scene(n=_lib.STATS_NOALLOC_MAX_N + 1)) == U
+    assert call(_scene(n=1 << 31)) == U
