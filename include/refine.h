@@ -68,9 +68,11 @@ typedef enum {
  *   SH coefficients.
  * These are the 59 parameters per primitive of Eq. 1 (Sec. 3.1).  Planes
  * 0..10 are stored as `dtype`, planes 11..58 as `sh_dtype`; the supported
- * pairs are (REFINE_F32, REFINE_F32) (4-byte elements) and
+ * pairs are (REFINE_F32, REFINE_F32) (4-byte elements),
  * (REFINE_BF16, REFINE_F16) (2-byte elements: BF16 geometry and opacity, FP16
- * colour); other pairs return REFINE_E_UNSUPPORTED.
+ * colour) and (REFINE_F16, REFINE_F16) (2-byte elements, all FP16: centres
+ * kept to 11 significant bits instead of BF16's 8); other pairs return
+ * REFINE_E_UNSUPPORTED.
  * n >= 0, stride >= n, n <= 2^31 - 1.  For an output scene (refine_compact)
  * n is the capacity in primitives.
  */
@@ -238,23 +240,28 @@ refine_status refine_score(const refine_scene* scene, const float* d_cams, int32
  * refine_score in two phases (refine_score = prepare, then views):
  *  refine_score_prepare  builds the per-view constant tables and, on the
  *                        binned path, the spatially binned, activated copy of
- *                        the scene in the workspace.  It depends only on the
- *                        scene, the cameras, the parameters and d_stats.
- *  refine_score_cameras  rebuilds only the per-view tables, for a new camera
- *                        set (any n_views the workspace was sized for; the
- *                        scene fixes the workspace layout, its planes are not
- *                        read).  The binned copy of the scene does not
+ *                        the scene in the workspace, then the views each group
+ *                        of binned primitives keeps (the conservative frustum
+ *                        test) and the order the view loop takes the groups
+ *                        in.  It depends only on the scene, the cameras, the
+ *                        parameters and d_stats.
+ *  refine_score_cameras  rebuilds what depends on the cameras -- the per-view
+ *                        tables and, on the binned path, the groups' kept
+ *                        views and order -- for a new camera set (any n_views
+ *                        the workspace was sized for; the scene's planes are
+ *                        not read).  The binned copy of the scene does not
  *                        depend on the cameras, so a scene prepared once can
  *                        be scored for many camera sets: prepare once, then
  *                        cameras + views per camera set, with the same scene,
  *                        params and d_stats.
  *  refine_score_views    evaluates every (primitive, view) pair that can
- *                        contribute and writes d_scores.  It reads the tables
- *                        the last prepare / cameras call on the same
+ *                        contribute and writes d_scores: one kernel launch
+ *                        (plus one when d_evaluated is given).  It reads the
+ *                        tables the last prepare / cameras call on the same
  *                        workspace built, so the same scene, n_views, params
- *                        and d_stats must be passed (scene->planes is read
- *                        only on the direct path).  Several views calls may
- *                        follow one prepare.
+ *                        (records_per_lane included) and d_stats must be
+ *                        passed (scene->planes is read only on the direct
+ *                        path).  Several views calls may follow one prepare.
  *  d_evaluated (nullable, device int64[2]) receives [0] the number of pairs
  *  the view loop evaluated in full and [1] the number it screened out after
  *  their first step (the camera-space centre and its distance outside the

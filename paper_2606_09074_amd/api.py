@@ -4,9 +4,10 @@ PyTorch provides device memory and the current HIP stream; every step of
 the computation runs in the library's HIP kernels.  The functions only
 check tensor shapes/dtypes/devices and pass pointers.
 
-A scene is a [59, stride] tensor: float32 for FP32 storage, or int16
-holding the raw bits of BF16 planes 0..10 and FP16 planes 11..58 (the
-mixed 2-byte storage; see synth.quantize_bf16_f16).
+A scene is a [59, stride] tensor: float32 for FP32 storage; int16 holding
+the raw bits of BF16 planes 0..10 and FP16 planes 11..58 (the mixed 2-byte
+storage; see synth.quantize_bf16_f16); or float16 for FP16 planes
+throughout (the half 2-byte storage; see synth.quantize_f16).
 """
 from __future__ import annotations
 
@@ -40,7 +41,10 @@ def storage_dtypes(planes: torch.Tensor) -> tuple[int, int]:
         return _lib.REFINE_F32, _lib.REFINE_F32
     if planes.dtype == torch.int16:
         return _lib.REFINE_BF16, _lib.REFINE_F16
-    raise ValueError("scene planes must be float32, or int16 bit patterns of BF16 (planes 0..10) and FP16 (11..58)")
+    if planes.dtype == torch.float16:
+        return _lib.REFINE_F16, _lib.REFINE_F16
+    raise ValueError("scene planes must be float32, float16, or int16 bit patterns of BF16 (planes 0..10) and "
+                     "FP16 (11..58)")
 
 
 def _scene(planes: torch.Tensor, n: Optional[int] = None) -> Scene:

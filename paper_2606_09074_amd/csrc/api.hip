@@ -25,7 +25,10 @@ bool finite(double x) { return std::isfinite(x); }
 bool known_dtype(int32_t d) { return d == REFINE_F32 || d == REFINE_BF16 || d == REFINE_F16; }
 
 // Storage format of a scene (call after check_scene succeeded).
-int storage_of(const refine_scene* s) { return s->dtype == REFINE_F32 ? kStoreF32 : kStoreBF16F16; }
+int storage_of(const refine_scene* s)
+{
+    return s->dtype == REFINE_F32 ? kStoreF32 : (s->dtype == REFINE_BF16 ? kStoreBF16F16 : kStoreF16);
+}
 
 refine_status check_scene(const refine_scene* s)
 {
@@ -34,7 +37,8 @@ refine_status check_scene(const refine_scene* s)
     if (!known_dtype(s->dtype) || !known_dtype(s->sh_dtype)) return REFINE_E_INVALID;
     const bool f32 = s->dtype == REFINE_F32 && s->sh_dtype == REFINE_F32;
     const bool mixed = s->dtype == REFINE_BF16 && s->sh_dtype == REFINE_F16;
-    if (!f32 && !mixed) return REFINE_E_UNSUPPORTED;
+    const bool half = s->dtype == REFINE_F16 && s->sh_dtype == REFINE_F16;
+    if (!f32 && !mixed && !half) return REFINE_E_UNSUPPORTED;
     if (s->n > (int64_t)std::numeric_limits<int32_t>::max()) return REFINE_E_UNSUPPORTED;
     if (s->stride > std::numeric_limits<int64_t>::max() / (kPlanes * 4)) return REFINE_E_INVALID;
     if (s->n > 0 && !s->planes) return REFINE_E_INVALID;
@@ -305,7 +309,7 @@ refine_status refine_score_cameras(const refine_scene* scene, const float* d_cam
     if (n_views > kMaxViews) return REFINE_E_UNSUPPORTED;
     Workspace ws;
     if ((s = check_workspace(scene->n, n_views, true, d_ws, ws_bytes, &ws)) != REFINE_OK) return s;
-    const hipError_t e = launch_score_cameras(d_cams, n_views, *params, ws, static_cast<hipStream_t>(stream));
+    const hipError_t e = launch_score_cameras(d_cams, n_views, scene->n, *params, ws, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? REFINE_OK : REFINE_E_HIP;
 }
 

@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <type_traits>
 
 #include "../../include/refine.h"
 
@@ -17,8 +18,20 @@ constexpr int kGeomPlanes = 11;    // planes stored in the scene's dtype; the re
 // Supported scene storage formats (dtype of planes 0..10, dtype of 11..58).
 enum Storage : int {
     kStoreF32 = 0,       // FP32, FP32
-    kStoreBF16F16 = 1    // BF16, FP16
+    kStoreBF16F16 = 1,   // BF16, FP16
+    kStoreF16 = 2        // FP16, FP16
 };
+
+// Calls f with the storage format as a compile-time constant.
+template <class F>
+inline void with_storage(int st, F&& f)
+{
+    switch (st) {
+    case kStoreF32: f(std::integral_constant<int, kStoreF32>{}); break;
+    case kStoreBF16F16: f(std::integral_constant<int, kStoreBF16F16>{}); break;
+    default: f(std::integral_constant<int, kStoreF16>{}); break;
+    }
+}
 
 __host__ __device__ inline size_t storage_bytes(int st) { return st == kStoreF32 ? 4 : 2; }
 constexpr int kCamFields = 18;
@@ -228,8 +241,8 @@ hipError_t launch_score_batch(const BatchJob* d_jobs, int n_jobs, int total_bloc
                               hipStream_t stream);
 hipError_t launch_select_batch(const BatchJob* d_jobs, int n_jobs, int total_tiles, hipStream_t stream);
 hipError_t launch_compact_batch(const BatchJob* d_jobs, int n_jobs, int total_tiles, hipStream_t stream);
-hipError_t launch_score_cameras(const float* d_cams, int32_t n_views, const refine_params& prm, const Workspace& ws,
-                                hipStream_t stream);
+hipError_t launch_score_cameras(const float* d_cams, int32_t n_views, int64_t n, const refine_params& prm,
+                                const Workspace& ws, hipStream_t stream);
 hipError_t launch_score_views(const void* planes, int st, int64_t stride, int64_t n, int32_t n_views,
                               const refine_params& prm, const refine_stats_t* d_stats, float* d_scores,
                               int64_t* d_evaluated, const Workspace& ws, hipStream_t stream);
@@ -272,8 +285,17 @@ __device__ inline uint32_t wave_sum_u32(uint32_t v)
     return v;
 }
 
-// Plane p of primitive i as FP32.  BF16 widens exactly (its bits are the
-// high half of an FP32), FP16 converts exactly (every half is a float).
+// A 2-byte element of plane p as FP32, exactly: BF16 (its bits are the high
+// half of an FP32) for the geometry planes of kStoreBF16F16, FP16 (every
+// half is a float) otherwise.
+template <int ST>
+__device__ __forceinline__ float widen2(uint16_t b, int p)
+{
+    if (ST == kStoreBF16F16 && p < kGeomPlanes) return __uint_as_float((uint32_t)b << 16);
+    return (float)__builtin_bit_cast(_Float16, b);
+}
+
+// Plane p of primitive i as FP32.
 template <int ST>
 __device__ __forceinline__ float load_plane(const void* __restrict__ planes, int64_t stride, int p, int64_t i)
 {
@@ -281,9 +303,7 @@ __device__ __forceinline__ float load_plane(const void* __restrict__ planes, int
     if constexpr (ST == kStoreF32) {
         return static_cast<const float*>(planes)[at];
     } else {
-        const uint16_t b = static_cast<const uint16_t*>(planes)[at];
-        if (p < kGeomPlanes) return __uint_as_float((uint32_t)b << 16);
-        return (float)__builtin_bit_cast(_Float16, b);
+        return widen2<ST>(static_cast<const uint16_t*>(planes)[at], p);
     }
 }
 

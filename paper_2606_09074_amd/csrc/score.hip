@@ -151,13 +151,17 @@ __device__ __forceinline__ void camera_prep_body(const float* __restrict__ cams,
     cull[j] = q;
 }
 
-// Also clears the binning cell counts (cell_cnt is null on the direct path).
+// Also clears the binning cell counts (cell_cnt is null when the scene is
+// not binned) and the work-class counts the culling adds into (aux is null
+// on the direct path).
 __global__ __launch_bounds__(kBlock) void camera_prep(const float* __restrict__ cams, int n_views, int nv,
                                                         float clamp_k, CamRec* __restrict__ out,
-                                                        CullRec* __restrict__ cull, uint32_t* __restrict__ cell_cnt)
+                                                        CullRec* __restrict__ cull, uint32_t* __restrict__ cell_cnt,
+                                                        uint32_t* __restrict__ aux)
 {
     const int j = blockIdx.x * kBlock + threadIdx.x;
     if (cell_cnt && j < kCells * kBinCopies) cell_cnt[j] = 0u;
+    if (aux && j < kOrderBuckets * kOrderCopies) aux[kOrderBuckets + j] = 0u;
     if (j < nv) camera_prep_body(cams, n_views, nv, clamp_k, out, cull, j);
 }
 
@@ -358,8 +362,10 @@ __global__ __launch_bounds__(kBlock) void score_opacity_batch(const BatchJob* __
     const int i = ((int)blockIdx.x - b.block0) * kBlock + (int)threadIdx.x;
     if (b.st == kStoreF32)
         score_opacity_body<kStoreF32>(b.planes, b.stride, b.n, b.scores, i);
-    else
+    else if (b.st == kStoreBF16F16)
         score_opacity_body<kStoreBF16F16>(b.planes, b.stride, b.n, b.scores, i);
+    else
+        score_opacity_body<kStoreF16>(b.planes, b.stride, b.n, b.scores, i);
 }
 
 template <int PROJ>
@@ -371,9 +377,12 @@ __global__ __launch_bounds__(kBlock) void score_direct_batch(const BatchJob* __r
     if (b.st == kStoreF32)
         score_direct_body<PROJ, kStoreF32>(b.planes, b.stride, b.n, b.cam_rec, b.nv, b.stats, eta, z_near,
                                            vis_alpha, b.scores, i);
-    else
+    else if (b.st == kStoreBF16F16)
         score_direct_body<PROJ, kStoreBF16F16>(b.planes, b.stride, b.n, b.cam_rec, b.nv, b.stats, eta, z_near,
                                                vis_alpha, b.scores, i);
+    else
+        score_direct_body<PROJ, kStoreF16>(b.planes, b.stride, b.n, b.cam_rec, b.nv, b.stats, eta, z_near,
+                                           vis_alpha, b.scores, i);
 }
 
 // ------------------------------------------------------------- binned path
@@ -590,11 +599,8 @@ __device__ inline float seg_max(float x)
 }
 
 __global__ __launch_bounds__(kBlock) void group_bounds(const PrimRec* __restrict__ recs, int n,
-                                                         GroupBound* __restrict__ gb, int ngroups,
-                                                         uint32_t* __restrict__ aux)
+                                                         GroupBound* __restrict__ gb, int ngroups)
 {
-    // the class counts start at zero for the first view loop
-    if (blockIdx.x == 0 && threadIdx.x < kOrderBuckets * kOrderCopies) aux[kOrderBuckets + threadIdx.x] = 0u;
     const int t = blockIdx.x * kBlock + threadIdx.x;
     const int g = t / kBoundLanes, sl = t % kBoundLanes;
     const bool ok = g < ngroups;   // whole 16-lane segments
@@ -770,9 +776,9 @@ __global__ __launch_bounds__(kCullThreads) void cull_groups(const GroupBound* __
     __shared__ GroupBound sb[kCullBlockGroups];
     __shared__ uint32_t part[kCullWaves][kCullBlockGroups];
     __shared__ uint32_t hist[kOrderBuckets];
-    // the class counts are cleared before this kernel (by group_bounds, then
-    // by each view loop); the cursors aux[0, kOrderBuckets) and the pair
-    // counters are used only by the kernels after it
+    // the class counts are cleared before this kernel (by camera_prep); the
+    // cursors aux[0, kOrderBuckets) are used only by the kernels after it,
+    // and the pair counters start from zero for the next view loop
     if (blockIdx.x == 0) {
         if (threadIdx.x < kOrderBuckets) aux[threadIdx.x] = 0u;
         if (evaluated && threadIdx.x < 2 * kEvalSlots) evaluated[threadIdx.x] = 0ull;
@@ -869,8 +875,7 @@ __global__ __launch_bounds__(kBlock) void score_binned(const PrimRec* __restrict
                                                          const uint64_t* __restrict__ mask,
                                                          const int32_t* __restrict__ order, int ngroups, int nv,
                                                          float eta, float z_near, float* __restrict__ out,
-                                                         unsigned long long* __restrict__ evaluated,
-                                                         uint32_t* __restrict__ aux)
+                                                         unsigned long long* __restrict__ evaluated)
 {
     const int lane = threadIdx.x & 63;
     // wave-uniform values (readfirstlane tells the compiler so: the mask
@@ -878,8 +883,6 @@ __global__ __launch_bounds__(kBlock) void score_binned(const PrimRec* __restrict
     // runs on the scalar unit)
     const int w = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * kBlock + threadIdx.x) >> 6);
     const bool active = w < ngroups;   // waves past the last group still help load the camera table
-    // (place_groups has read the class counts: clear them for the next view loop)
-    if (blockIdx.x == 0 && threadIdx.x < kOrderBuckets * kOrderCopies) aux[kOrderBuckets + threadIdx.x] = 0u;
     const int G = active ? min(max(__builtin_amdgcn_readfirstlane(order[w]), 0), ngroups - 1) : 0;
     const int g0 = G * kGroup * PPL;
     Prim p[PPL];
@@ -928,7 +931,7 @@ __global__ __launch_bounds__(kBlock) void score_binned(const PrimRec* __restrict
                     hd[k] = pair_head(c, p[k]);
                     may = may || pair_may_pass(hd[k], c.kvs, smax[k], z_near);
                 }
-                const bool live = __ballot(may) != 0ull;
+                const bool live = __builtin_amdgcn_ballot_w64(may) != 0ull;
                 if (VPI == 2 && m != 0ull) {
                     const int b2 = __builtin_ctzll(m);
                     m &= m - 1ull;
@@ -958,11 +961,12 @@ __global__ __launch_bounds__(kBlock) void score_binned(const PrimRec* __restrict
                         for (int k = 0; k < PPL; ++k) pair_tail<PROJ>(c2, p[k], hd2[k], eta, z_near);
                     }
                 } else {
-                    n_eval += live ? 1u : 0u;
-                    n_screened += live ? 0u : 1u;
                     if (live) {
+                        ++n_eval;
 #pragma unroll
                         for (int k = 0; k < PPL; ++k) pair_tail<PROJ>(c, p[k], hd[k], eta, z_near);
+                    } else {
+                        ++n_screened;
                     }
                 }
             }
@@ -981,12 +985,15 @@ __global__ __launch_bounds__(kBlock) void score_binned(const PrimRec* __restrict
 
 // out[0]: pairs evaluated in full, out[1]: pairs screened out after their
 // first step (the direct path evaluates every pair).
-__global__ void counter_store(const unsigned long long* c, int64_t* out, int64_t direct_pairs)
+// The counters restart from zero for the next view loop.
+__global__ void counter_store(unsigned long long* c, int64_t* out, int64_t direct_pairs)
 {
     unsigned long long t = 0, sc = 0;
     for (int s = 0; s < kEvalSlots; ++s) {
         t += c[s];
         sc += c[kEvalSlots + s];
+        c[s] = 0ull;
+        c[kEvalSlots + s] = 0ull;
     }
     out[0] = direct_pairs >= 0 ? direct_pairs : (int64_t)t;
     out[1] = direct_pairs >= 0 ? 0 : (int64_t)sc;
@@ -1007,7 +1014,29 @@ void prepare_mode(const void* planes, int64_t stride, int n, const refine_params
                        ws.recs);
     const int ng = (int)num_groups(n, kGroup);
     hipLaunchKernelGGL(group_bounds, dim3((unsigned)num_groups(ng, kBlock / kBoundLanes)), dim3(kBlock), 0, stream,
-                       ws.recs, n, ws.gbound, ng, ws.gaux);
+                       ws.recs, n, ws.gbound, ng);
+}
+
+int records_per_lane(const refine_params& prm) { return prm.records_per_lane > 0 ? prm.records_per_lane : kDefaultPPL; }
+
+// The camera-set dependent stage of the binned path: each view-loop group's
+// kept views (cull_groups) and the groups' order (place_groups).  Clears the
+// pair counters of the next view loop.
+void cull_and_order(int n, int nv, const refine_params& prm, const Workspace& ws, hipStream_t stream)
+{
+    const float zn = (float)prm.z_near;
+    const int ppl = records_per_lane(prm);
+    const int ng64 = (int)num_groups(n, kGroup);
+    const int ng = (int)num_groups(n, kGroup * ppl);
+    const unsigned gblocks = (unsigned)num_groups(ng, kBlock);
+    const unsigned cblocks = (unsigned)num_groups(ng, kCullBlockGroups);
+    if (ppl == 2)
+        hipLaunchKernelGGL(cull_groups<2>, dim3(cblocks), dim3(kCullThreads), 0, stream, ws.gbound, ng64, ng, ws.culls,
+                           nv, zn, ws.gmask, ws.gcount, ws.gaux, ws.evaluated);
+    else
+        hipLaunchKernelGGL(cull_groups<1>, dim3(cblocks), dim3(kCullThreads), 0, stream, ws.gbound, ng64, ng, ws.culls,
+                           nv, zn, ws.gmask, ws.gcount, ws.gaux, ws.evaluated);
+    hipLaunchKernelGGL(place_groups, dim3(gblocks), dim3(kBlock), 0, stream, ws.gcount, ng, nv, ws.gaux, ws.gorder);
 }
 
 template <int PROJ, int ST>
@@ -1019,24 +1048,13 @@ void views_mode(const void* planes, int64_t stride, int n, const refine_params& 
     const float eta = (float)prm.eta, zn = (float)prm.z_near;
     const dim3 grid((unsigned)((n + kBlock - 1) / kBlock));
     if (binned) {
-        const int ppl = prm.records_per_lane > 0 ? prm.records_per_lane : kDefaultPPL;
-        const int ng64 = (int)num_groups(n, kGroup);
+        const int ppl = records_per_lane(prm);
         const int ng = (int)num_groups(n, kGroup * ppl);
-        const unsigned gblocks = (unsigned)num_groups(ng, kBlock);
         const unsigned loop_blocks = (unsigned)num_groups(ng, kWaves);
-        uint32_t* const counts = ws.gcount;
-        const unsigned cblocks = (unsigned)num_groups(ng, kCullBlockGroups);
-        if (ppl == 2)
-            hipLaunchKernelGGL(cull_groups<2>, dim3(cblocks), dim3(kCullThreads), 0, stream, ws.gbound, ng64, ng, ws.culls,
-                               nv, zn, ws.gmask, counts, ws.gaux, evaluated);
-        else
-            hipLaunchKernelGGL(cull_groups<1>, dim3(cblocks), dim3(kCullThreads), 0, stream, ws.gbound, ng64, ng, ws.culls,
-                               nv, zn, ws.gmask, counts, ws.gaux, evaluated);
-        hipLaunchKernelGGL(place_groups, dim3(gblocks), dim3(kBlock), 0, stream, counts, ng, nv, ws.gaux, ws.gorder);
         const int vpi = prm.views_per_iteration > 0 ? prm.views_per_iteration : kDefaultVPI;
         auto loop = [&](auto kernel) {
             hipLaunchKernelGGL(kernel, dim3(loop_blocks), dim3(kBlock), 0, stream, ws.recs, n, ws.cams, ws.gmask,
-                               ws.gorder, ng, nv, eta, zn, d_scores, evaluated, ws.gaux);
+                               ws.gorder, ng, nv, eta, zn, d_scores, evaluated);
         };
         if (ppl == 2)
             vpi == 2 ? loop(score_binned<PROJ, 2, 2>) : loop(score_binned<PROJ, 2, 1>);
@@ -1061,12 +1079,7 @@ bool binned_path(const refine_params& prm, int64_t n)
 template <class F>
 void dispatch_mode(int proj, int st, F&& f)
 {
-    auto by_storage = [&](auto proj_c) {
-        if (st == kStoreF32)
-            f(proj_c, std::integral_constant<int, kStoreF32>{});
-        else
-            f(proj_c, std::integral_constant<int, kStoreBF16F16>{});
-    };
+    auto by_storage = [&](auto proj_c) { with_storage(st, [&](auto st_c) { f(proj_c, st_c); }); };
     switch (proj) {
     case REFINE_PROJ_COV: by_storage(std::integral_constant<int, REFINE_PROJ_COV>{}); break;
     case REFINE_PROJ_DEPTH: by_storage(std::integral_constant<int, REFINE_PROJ_DEPTH>{}); break;
@@ -1083,11 +1096,13 @@ hipError_t launch_score_prepare(const void* planes, int st, int64_t stride, int6
     const bool binned = n > 0 && binned_path(prm, n);
     const int threads = binned ? (nv > kCells * kBinCopies ? nv : kCells * kBinCopies) : nv;
     hipLaunchKernelGGL(camera_prep, dim3((threads + kBlock - 1) / kBlock), dim3(kBlock), 0, stream, d_cams, n_views, nv,
-                       (float)prm.clamp_k, ws.cams, ws.culls, binned ? ws.cell_cnt : nullptr);
+                       (float)prm.clamp_k, ws.cams, ws.culls, binned ? ws.cell_cnt : nullptr,
+                       binned ? ws.gaux : nullptr);
     if (!binned) return hipGetLastError();
     dispatch_mode(prm.proj_mode, st, [&](auto proj_c, auto st_c) {
         prepare_mode<decltype(proj_c)::value, decltype(st_c)::value>(planes, stride, (int)n, prm, d_stats, ws, stream);
     });
+    cull_and_order((int)n, nv, prm, ws, stream);
     return hipGetLastError();
 }
 
@@ -1118,12 +1133,16 @@ hipError_t launch_score_batch(const BatchJob* d_jobs, int n_jobs, int total_bloc
     return hipGetLastError();
 }
 
-hipError_t launch_score_cameras(const float* d_cams, int32_t n_views, const refine_params& prm, const Workspace& ws,
-                                hipStream_t stream)
+hipError_t launch_score_cameras(const float* d_cams, int32_t n_views, int64_t n, const refine_params& prm,
+                                const Workspace& ws, hipStream_t stream)
 {
+    if (prm.score_kind == REFINE_SCORE_OPACITY) return hipSuccess;   // nothing depends on the cameras
     const int nv = views_of(prm, n_views);
-    hipLaunchKernelGGL(camera_prep, dim3((nv + kBlock - 1) / kBlock), dim3(kBlock), 0, stream, d_cams, n_views, nv,
-                       (float)prm.clamp_k, ws.cams, ws.culls, nullptr);
+    const bool binned = n > 0 && binned_path(prm, n);
+    const int threads = nv > kOrderBuckets * kOrderCopies ? nv : kOrderBuckets * kOrderCopies;
+    hipLaunchKernelGGL(camera_prep, dim3((threads + kBlock - 1) / kBlock), dim3(kBlock), 0, stream, d_cams, n_views, nv,
+                       (float)prm.clamp_k, ws.cams, ws.culls, nullptr, binned ? ws.gaux : nullptr);
+    if (binned) cull_and_order((int)n, nv, prm, ws, stream);
     return hipGetLastError();
 }
 
@@ -1134,17 +1153,15 @@ hipError_t launch_score_views(const void* planes, int st, int64_t stride, int64_
     const int nv = views_of(prm, n_views);
     const bool binned = binned_path(prm, n);
     unsigned long long* counter = (d_evaluated && binned) ? ws.evaluated : nullptr;
-    if (binned && n == 0 && counter)   // the view loop, which clears the pair counters, does not run
+    if (binned && n == 0 && counter)   // no culling stage has cleared the pair counters
         hipLaunchKernelGGL(views_init, dim3(1), dim3(2 * kEvalSlots), 0, stream, counter);
     if (prm.score_kind == REFINE_SCORE_OPACITY) {
         if (n > 0) {
             const dim3 grid((unsigned)((n + kBlock - 1) / kBlock));
-            if (st == kStoreF32)
-                hipLaunchKernelGGL(score_opacity<kStoreF32>, grid, dim3(kBlock), 0, stream, planes, stride, (int)n,
-                                   d_scores);
-            else
-                hipLaunchKernelGGL(score_opacity<kStoreBF16F16>, grid, dim3(kBlock), 0, stream, planes, stride,
+            with_storage(st, [&](auto st_c) {
+                hipLaunchKernelGGL(score_opacity<decltype(st_c)::value>, grid, dim3(kBlock), 0, stream, planes, stride,
                                    (int)n, d_scores);
+            });
         }
         if (d_evaluated)   // no pairs are evaluated
             hipLaunchKernelGGL(counter_store, dim3(1), dim3(1), 0, stream, ws.evaluated, d_evaluated, (int64_t)0);

@@ -190,9 +190,7 @@ __device__ __forceinline__ void stats_partial_vec_body(const void* __restrict__ 
                     if constexpr (ST == kStoreF32) {
                         v[p] = __uint_as_float(word);
                     } else {
-                        const uint16_t b = (uint16_t)((j & 1) ? (word >> 16) : (word & 0xFFFFu));
-                        v[p] = p < kGeomPlanes ? __uint_as_float((uint32_t)b << 16)
-                                               : (float)__builtin_bit_cast(_Float16, b);
+                        v[p] = widen2<ST>((uint16_t)((j & 1) ? (word >> 16) : (word & 0xFFFFu)), p);
                     }
                 }
                 a.add(v, eta);
@@ -317,10 +315,14 @@ __global__ __launch_bounds__(kBlock) void stats_partial_batch(const BatchJob* __
         stats_partial_vec_body<kStoreF32>(b.planes, b.stride, b.n, eta, b.stat_part, tile);
     else if (b.st == kStoreF32)
         stats_partial_body<kStoreF32>(b.planes, b.stride, b.n, eta, b.stat_part, tile);
-    else if (b.vec_stats)
+    else if (b.st == kStoreBF16F16 && b.vec_stats)
         stats_partial_vec_body<kStoreBF16F16>(b.planes, b.stride, b.n, eta, b.stat_part, tile);
-    else
+    else if (b.st == kStoreBF16F16)
         stats_partial_body<kStoreBF16F16>(b.planes, b.stride, b.n, eta, b.stat_part, tile);
+    else if (b.vec_stats)
+        stats_partial_vec_body<kStoreF16>(b.planes, b.stride, b.n, eta, b.stat_part, tile);
+    else
+        stats_partial_body<kStoreF16>(b.planes, b.stride, b.n, eta, b.stat_part, tile);
 }
 
 // Also sets up each job's selection (its state and cleared histograms): the
@@ -368,18 +370,15 @@ hipError_t launch_stats(const void* planes, int st, int64_t stride, int64_t n, c
     const int ntiles = (int)num_tiles(n);
     if (ntiles > 0) {
         const bool vec = reinterpret_cast<uintptr_t>(planes) % 16 == 0 && (stride * storage_bytes(st)) % 16 == 0;
-        if (st == kStoreF32 && vec)
-            hipLaunchKernelGGL(stats_partial_vec<kStoreF32>, dim3(ntiles), dim3(kBlock), 0, stream, planes, stride,
-                               (int)n, (float)prm.eta, ws.stat_part);
-        else if (st == kStoreF32)
-            hipLaunchKernelGGL(stats_partial<kStoreF32>, dim3(ntiles), dim3(kBlock), 0, stream, planes, stride,
-                               (int)n, (float)prm.eta, ws.stat_part);
-        else if (vec)
-            hipLaunchKernelGGL(stats_partial_vec<kStoreBF16F16>, dim3(ntiles), dim3(kBlock), 0, stream, planes,
-                               stride, (int)n, (float)prm.eta, ws.stat_part);
-        else
-            hipLaunchKernelGGL(stats_partial<kStoreBF16F16>, dim3(ntiles), dim3(kBlock), 0, stream, planes, stride,
-                               (int)n, (float)prm.eta, ws.stat_part);
+        with_storage(st, [&](auto st_c) {
+            constexpr int ST = decltype(st_c)::value;
+            if (vec)
+                hipLaunchKernelGGL(stats_partial_vec<ST>, dim3(ntiles), dim3(kBlock), 0, stream, planes, stride,
+                                   (int)n, (float)prm.eta, ws.stat_part);
+            else
+                hipLaunchKernelGGL(stats_partial<ST>, dim3(ntiles), dim3(kBlock), 0, stream, planes, stride, (int)n,
+                                   (float)prm.eta, ws.stat_part);
+        });
     }
     hipLaunchKernelGGL(stats_finalize, dim3(1), dim3(kBlock), 0, stream, ws.stat_part, ntiles, n, prm, d_stats);
     return hipGetLastError();

@@ -61,8 +61,10 @@ def run_gpu(planes: np.ndarray, cams: np.ndarray, n: int | None = None, ratio: f
                           n_keep_out=nk, threshold_out=thr, n=n)
         k = int(nk.item())
         cap = max(k, 0)
-        fill = float("nan") if pl.dtype == torch.float32 else INT16_FILL
-        out = torch.full((59, max(cap, 1) + 3), fill, dtype=pl.dtype, device=dev)
+        if pl.dtype == torch.float32:
+            out = torch.full((59, max(cap, 1) + 3), float("nan"), dtype=pl.dtype, device=dev)
+        else:   # 2-byte storage: a fill bit pattern
+            out = torch.full((59, max(cap, 1) + 3), INT16_FILL, dtype=torch.int16, device=dev).view(pl.dtype)
         idx = torch.full((max(cap, 1) + 3,), -7, dtype=torch.int32, device=dev)
         nout = torch.full((1,), -1, dtype=torch.int64, device=dev)
         api.refine_compact(pl, keep, out, ws, index_map_out=idx, n_out=nout, n=n, capacity=cap)
@@ -77,7 +79,7 @@ def run_gpu(planes: np.ndarray, cams: np.ndarray, n: int | None = None, ratio: f
     return res
 
 
-# what run_gpu pre-fills an int16 compaction output with (float32: NaN)
+# the bit pattern run_gpu pre-fills a 2-byte compaction output with (float32: NaN)
 INT16_FILL = -12345
 
 
@@ -94,10 +96,20 @@ def oracle_all(planes, cams, n=None, **kw):
 STATS_RTOL = 1e-6
 
 
-def check_stats(gs, F, lam, what):
+def check_stats(gs, F, lam, what, **kw):
+    """Features (FP32 per-primitive terms, FP64 sums) within STATS_RTOL of the
+    oracle's; lambda equal, to FP64 rounding, to Eq. 18-19 applied to the
+    GPU's own features (the derivation is FP64 on both sides, while its
+    logarithm amplifies the features' FP32 error by 1/|ln(F_gem + eta)|,
+    about 9 where F_gem + eta is near 0.9), and within a loose bound of the
+    oracle's lambda."""
+    import oracle
     for k in ("ybar", "f_col", "f_opa", "f_gem"):
         assert abs(gs[k] - F[k]) <= STATS_RTOL * abs(F[k]) + 1e-15, (what, k, gs[k], F[k])
-    np.testing.assert_allclose(gs["lambda"], lam, rtol=STATS_RTOL, atol=1e-12)
+    if gs["n"] > 0:
+        lam_gpu_features = oracle.lam({k: gs[k] for k in ("ybar", "f_col", "f_opa", "f_gem")}, oracle_params(**kw))
+        np.testing.assert_allclose(gs["lambda"], lam_gpu_features, rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(gs["lambda"], lam, rtol=50 * STATS_RTOL, atol=1e-12)
 
 
 def check_compact(planes, n, r):
@@ -111,7 +123,7 @@ def check_compact(planes, n, r):
     np.testing.assert_array_equal(r["out"][:, :k].view(bits), ref.view(bits))
     np.testing.assert_array_equal(r["index_map"][:k], np.nonzero(keep)[0].astype(np.int32))
     tail = r["out"][:, k:]
-    assert (np.all(np.isnan(tail)) if planes.dtype == np.float32 else np.all(tail == INT16_FILL))
+    assert (np.all(np.isnan(tail)) if planes.dtype == np.float32 else np.all(tail.view(np.int16) == INT16_FILL))
     assert np.all(r["index_map"][k:] == -7)
 
 
@@ -174,3 +186,11 @@ def workload(name: str, n: int | None = None):
     if n is not None:
         spec = spec.with_n(n)
     return synth.make_planes(spec), synth.make_cameras(spec), spec
+
+
+@functools.lru_cache(maxsize=2)
+def oracle_workload(name: str):
+    """Oracle statistics, weights and scores (with intervals) of a whole
+    named workload in FP32 storage, computed once per test session."""
+    planes, cams, _ = workload(name)
+    return oracle_all(planes, cams)

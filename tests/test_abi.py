@@ -109,7 +109,7 @@ def test_stats_validation(lib):
     assert call(_scene(sh_dtype=-1)) == E
     U = _lib.REFINE_E_UNSUPPORTED
     F32, BF16, F16 = _lib.REFINE_F32, _lib.REFINE_BF16, _lib.REFINE_F16
-    for dt, sh in ((F32, BF16), (F32, F16), (BF16, F32), (BF16, BF16), (F16, F16), (F16, BF16)):
+    for dt, sh in ((F32, BF16), (F32, F16), (BF16, F32), (BF16, BF16), (F16, F32), (F16, BF16)):
         assert call(_scene(dtype=dt, sh_dtype=sh)) == U, (dt, sh)
     assert call(_scene(n=1 << 31)) == _lib.REFINE_E_UNSUPPORTED
     assert call(_scene(), prm=None) == E

@@ -26,13 +26,16 @@ def _jobs():
     spec = [  # (n, stride, storage, views, ratio, capacity fraction)
         (1, 1, "f32", 16, 0.5, 1.0), (777, 777, "f32", 7, 0.3, 1.0), (4096, 4096, "mixed", 16, 0.9, 1.0),
         (4097, 4103, "f32", 33, 0.5, 1.0), (20000, 20000, "mixed", 50, 0.66, 1.0),
-        (50000, 50000, "f32", 16, 0.5, 0.8), (9001, 9003, "mixed", 5, 0.41, 1.0)]
+        (50000, 50000, "f32", 16, 0.5, 0.8), (9001, 9003, "mixed", 5, 0.41, 1.0),
+        (12345, 12352, "half", 24, 0.5, 1.0), (3001, 3003, "half", 9, 0.7, 0.9)]
     out = []
     for n, stride, store, V, ratio, capf in spec:
         pl = np.zeros((59, stride), np.float32)
         pl[:, :n] = base[:, :n]
         if store == "mixed":
             pl = synth.quantize_bf16_f16(pl)
+        elif store == "half":
+            pl = synth.quantize_f16(pl)
         out.append((pl, n, synth.ring_cameras(V), ratio, capf))
     return out
 
@@ -47,13 +50,14 @@ def test_batch_matches_single_scene_calls():
         pl = torch.from_numpy(pl_np).to(dev)
         cams = torch.from_numpy(cams_np).to(dev)
         cap = int((n - api.prune_count(n, ratio)) * capf)
-        fill = float("nan") if pl.dtype == torch.float32 else -12345
+        out = (torch.full((59, cap + 3), float("nan"), dtype=pl.dtype, device=dev) if pl.dtype == torch.float32
+               else torch.full((59, cap + 3), -12345, dtype=torch.int16, device=dev).view(pl.dtype))
         jobs.append({"planes": pl, "n": n, "cams": cams, "ratio": ratio,
                      "stats": torch.zeros(_lib.STATS_BYTES, dtype=torch.uint8, device=dev),
                      "scores": torch.full((n,), float("nan"), dtype=torch.float32, device=dev),
                      "keep": torch.full((n,), 7, dtype=torch.uint8, device=dev),
                      "n_keep": torch.full((1,), -1, dtype=torch.int64, device=dev),
-                     "out": torch.full((59, cap + 3), fill, dtype=pl.dtype, device=dev), "capacity": cap,
+                     "out": out, "capacity": cap,
                      "index_map": torch.full((cap + 3,), -7, dtype=torch.int32, device=dev),
                      "n_out": torch.full((1,), -1, dtype=torch.int64, device=dev)})
         singles.append(run_gpu(pl_np, cams_np, n=n, ratio=ratio, params=gpu_params(score_path=1)))
@@ -79,8 +83,9 @@ def test_batch_matches_single_scene_calls():
         np.testing.assert_array_equal(out[:, :cap].view(bits), pl_np[:, sel].view(bits))
         np.testing.assert_array_equal(j["index_map"].cpu().numpy()[:cap], sel.astype(np.int32))
         tail = out[:, cap:]
-        assert np.all(np.isnan(tail)) if pl_np.dtype == np.float32 else np.all(tail == -12345)
-        deq = pl_np if pl_np.dtype == np.float32 else synth.dequantize_bf16_f16(pl_np)
+        assert np.all(np.isnan(tail)) if pl_np.dtype == np.float32 else np.all(tail.view(np.int16) == -12345)
+        deq = {np.dtype(np.float32): lambda x: x, np.dtype(np.int16): synth.dequantize_bf16_f16,
+               np.dtype(np.float16): synth.dequantize_f16}[pl_np.dtype](pl_np)
         F, lam, D, lo, hi = oracle_all(deq, cams_np, n=n)
         check_scores(j["scores"].cpu().numpy(), D, lo, hi, what)
 

@@ -84,7 +84,7 @@ def test_method_switches(mode):
     sub = np.ascontiguousarray(planes[:, :20000])
     F, lam, D, lo, hi = oracle_all(sub, cams, **mode)
     r = run_gpu(sub, cams, params=gpu_params(**mode))
-    check_stats(r["stats"], F, lam, str(mode))
+    check_stats(r["stats"], F, lam, str(mode), **mode)
     check_scores(r["scores"], D, lo, hi, str(mode))
 
 

@@ -1,7 +1,8 @@
-"""GPU parity of the 2-byte scene storage (planes 0..10 BF16, planes 11..58
-FP16, FP32 arithmetic) against the FP64 oracle on the dequantised inputs,
-with the same tolerances as the FP32 storage; and the effect of the storage
-itself (scores and kept sets against the FP32 scene).
+"""GPU parity of the 2-byte scene storages -- mixed (planes 0..10 BF16,
+planes 11..58 FP16) and half (every plane FP16), FP32 arithmetic either way --
+against the FP64 oracle on the dequantised inputs, with the same tolerances
+as the FP32 storage; and the effect of the storage itself (scores and kept
+sets against the FP32 scene, on the GPU and in the FP64 oracle).
 
 The storage changes the inputs, not the arithmetic: the oracle runs on the
 exact values the 2-byte planes hold, so the parity bar is unchanged.
@@ -29,6 +30,14 @@ def _mixed(planes):
     return q, synth.dequantize_bf16_f16(q)
 
 
+def _half(planes):
+    h = synth.quantize_f16(planes)
+    return h, synth.dequantize_f16(h)
+
+
+FORMATS = {"mixed": _mixed, "half": _half}
+
+
 def _pipeline(q, deq, cams, n, ratios, what):
     """Stats, scores, then for each ratio the mask and compaction, all
     against the oracle on the dequantised scene; returns the last run."""
@@ -47,41 +56,45 @@ def _pipeline(q, deq, cams, n, ratios, what):
     return r
 
 
-def test_small_mixed_full_pipeline():
+@pytest.mark.parametrize("fmt", ["mixed", "half"])
+def test_small_two_byte_full_pipeline(fmt):
     planes, cams, spec = workload("small")
-    q, deq = _mixed(planes)
-    log(f"small mixed: n={spec.n} V={cams.shape[0]}")
-    _pipeline(q, deq, cams, spec.n, 0.5, "small mixed")
+    q, deq = FORMATS[fmt](planes)
+    log(f"small {fmt}: n={spec.n} V={cams.shape[0]}")
+    _pipeline(q, deq, cams, spec.n, 0.5, f"small {fmt}")
 
 
+@pytest.mark.parametrize("fmt", ["mixed", "half"])
 @pytest.mark.parametrize("n", [1, 65, 4095, 4097, 9000])
-def test_mixed_ragged_sizes(n):
+def test_two_byte_ragged_sizes(n, fmt):
     planes, cams, _ = workload("small")
-    q, deq = _mixed(np.ascontiguousarray(planes[:, :n]))
-    log(f"mixed ragged n={n}")
-    _pipeline(q, deq, cams, n, 0.5, f"mixed n={n}")
+    q, deq = FORMATS[fmt](np.ascontiguousarray(planes[:, :n]))
+    log(f"{fmt} ragged n={n}")
+    _pipeline(q, deq, cams, n, 0.5, f"{fmt} n={n}")
 
 
+@pytest.mark.parametrize("fmt", ["mixed", "half"])
 @pytest.mark.parametrize("stride_pad", [0, 3])
-def test_mixed_padded_stride(stride_pad):
+def test_two_byte_padded_stride(stride_pad, fmt):
     """stride % 4 == 3 sends the compaction to its scalar kernel."""
     planes, cams, _ = workload("small")
     n = 5000
-    q, deq = _mixed(np.ascontiguousarray(planes[:, :n]))
-    qp = np.full((59, n + stride_pad), 0x7C01, dtype=np.int16)   # FP16 NaN / BF16 huge: must never be read
+    q, deq = FORMATS[fmt](np.ascontiguousarray(planes[:, :n]))
+    qp = np.full((59, n + stride_pad), 0x7C01, dtype=np.int16).view(q.dtype)   # FP16 NaN / BF16 huge: never read
     qp[:, :n] = q
-    log(f"mixed padded stride {n + stride_pad}")
-    _pipeline(qp, deq, cams, n, 0.3, f"mixed stride={n + stride_pad}")
+    log(f"{fmt} padded stride {n + stride_pad}")
+    _pipeline(qp, deq, cams, n, 0.3, f"{fmt} stride={n + stride_pad}")
 
 
+@pytest.mark.parametrize("fmt", ["mixed", "half"])
 @pytest.mark.parametrize("name,n", [("small", None), ("medium", 400_000)])
-def test_mixed_binned_and_direct_paths_bit_identical(name, n):
+def test_two_byte_binned_and_direct_paths_bit_identical(name, n, fmt):
     planes, cams, _ = workload(name)
-    q, _ = _mixed(np.ascontiguousarray(planes[:, :n]) if n else planes)
+    q, _ = FORMATS[fmt](np.ascontiguousarray(planes[:, :n]) if n else planes)
     d = run_gpu(q, cams, params=gpu_params(score_path=1))
     b = run_gpu(q, cams, params=gpu_params(score_path=2))
     np.testing.assert_array_equal(b["scores"].view(np.uint32), d["scores"].view(np.uint32))
-    log(f"[mixed paths {name} n={q.shape[1]}] identical")
+    log(f"[{fmt} paths {name} n={q.shape[1]}] identical")
 
 
 def test_mixed_nonfinite_inputs_are_counted():
@@ -94,49 +107,81 @@ def test_mixed_nonfinite_inputs_are_counted():
     assert r["stats"]["n_nonfinite"] == 2
 
 
+def test_half_nonfinite_inputs_are_counted():
+    """FP16 infinities and NaNs, including a centre beyond the half range
+    (which the conversion turns into an infinity)."""
+    planes, cams, _ = workload("small")
+    sub = np.ascontiguousarray(planes[:, :2000]).copy()
+    sub[1, 9] = 1e5                              # beyond 65504
+    h, _ = _half(sub)
+    h[4, 30] = np.float16(np.nan)                # log-scale
+    h[13, 31] = np.float16(-np.inf)              # colour
+    h[50, 32] = np.float16(np.nan)               # higher SH: not read by the scoring
+    r = run_gpu(h, cams)
+    assert r["stats"]["n_nonfinite"] == 3
+
+
 def _jaccard(a, b):
     a, b = a.astype(bool), b.astype(bool)
     return float((a & b).sum()) / float((a | b).sum())
 
 
+def _keep(scores, k):
+    return expected_keep_from_scores(scores, k).astype(bool)
+
+
 @pytest.mark.slow
-def test_medium_mixed_parity_and_storage_effect():
+@pytest.mark.parametrize("fmt", ["mixed", "half"])
+def test_medium_two_byte_parity_and_storage_effect(fmt):
     """3M x 200: every score of the 2-byte scene against the oracle on the
-    dequantised scene; then the storage effect against the FP32 scene (kept-set
-    Jaccard at beta 0.5 and 0.9, score relative error)."""
+    dequantised scene, masks at beta 0.9 and 0.5; then the storage effect
+    against the FP32 scene (score relative error, kept-set Jaccard at beta
+    0.5 and 0.9), both GPU to GPU and against the FP64 oracle's scores of the
+    FP32 scene.  The half format keeps Jaccard >= 0.995 against both; the
+    mixed format's BF16 centres (8 significant bits: up to 0.06 world units
+    at |x| = 20) move enough primitives across the beta = 0.9 threshold to
+    stay near 0.99."""
+    from tests.gpu_common import oracle_workload
     planes, cams, spec = workload("medium")
-    q, deq = _mixed(planes)
-    log(f"medium mixed: n={spec.n} V={cams.shape[0]}")
-    r16 = _pipeline(q, deq, cams, spec.n, (0.9, 0.5), "medium mixed")
+    q, deq = FORMATS[fmt](planes)
+    log(f"medium {fmt}: n={spec.n} V={cams.shape[0]}")
+    r16 = _pipeline(q, deq, cams, spec.n, (0.9, 0.5), f"medium {fmt}")
     r32 = run_gpu(planes, cams)
+    D64 = oracle_workload("medium")[2]
     s16, s32 = r16["scores"].astype(np.float64), r32["scores"].astype(np.float64)
     nz = s32 > 0
     rel = np.abs(s16[nz] - s32[nz]) / s32[nz]
-    out = {"rel_median": float(np.median(rel)), "rel_p99": float(np.quantile(rel, 0.99))}
+    nzo = D64 > 0
+    rel_o = np.abs(s16[nzo] - D64[nzo]) / D64[nzo]
+    out = {"rel_median": float(np.median(rel)), "rel_p99": float(np.quantile(rel, 0.99)),
+           "rel_vs_oracle_median": float(np.median(rel_o)), "rel_vs_oracle_p99": float(np.quantile(rel_o, 0.99))}
+    import oracle
     for beta in (0.5, 0.9):
         k = int(np.floor(beta * spec.n + 0.5))
-        out[f"jaccard_kept_{beta}"] = _jaccard(expected_keep_from_scores(r16["scores"], k),
-                                               expected_keep_from_scores(r32["scores"], k))
-    log(f"[medium storage effect] {out}")
-    # BF16 centres move by up to 2^-9 |x| (0.04 world units at |x| = 20): the
-    # storage shifts scores by ~0.3% typically; the kept sets stay close
-    assert out["jaccard_kept_0.5"] >= 0.99 and out["jaccard_kept_0.9"] >= 0.98, out
+        out[f"jaccard_kept_{beta}"] = _jaccard(_keep(r16["scores"], k), _keep(r32["scores"], k))
+        keep_o, _ = oracle.select(D64, k)
+        out[f"jaccard_kept_vs_oracle_{beta}"] = _jaccard(_keep(r16["scores"], k), keep_o.astype(bool))
+    log(f"[medium {fmt} storage effect] {out}")
+    floor = {"half": (0.995, 0.995), "mixed": (0.99, 0.98)}[fmt]
+    for tag in ("jaccard_kept_", "jaccard_kept_vs_oracle_"):
+        assert out[tag + "0.5"] >= floor[0] and out[tag + "0.9"] >= floor[1], out
 
 
+@pytest.mark.parametrize("fmt", ["mixed", "half"])
 @pytest.mark.parametrize("n,stride,mask_offset,even_out,cap_frac",
                          [(9000, 9000, 0, True, 1.0),      # 16-byte loads, paired 2-byte stores
                           (9000, 9000, 0, False, 1.0),     # odd output stride: single 2-byte stores
                           (8999, 9008, 0, True, 0.6),      # ragged tail, capacity below the survivors
                           (9001, 9003, 1, True, 1.0),      # stride not a multiple of 8, unaligned mask: scalar
                           (20000, 20000, 0, True, 0.97)])
-def test_mixed_compact_kernels(n, stride, mask_offset, even_out, cap_frac):
+def test_two_byte_compact_kernels(n, stride, mask_offset, even_out, cap_frac, fmt):
     """2-byte compaction: the 16-byte-load kernel with paired or single stores
     and the scalar fallback copy the survivors bit for bit, stably (tiles
     start at odd and even output offsets)."""
     import torch
 
     from paper_2606_09074_amd import api
-    planes = synth.quantize_bf16_f16(synth.make_planes(synth.SMALL.with_n(n), stride=stride))
+    planes = FORMATS[fmt](synth.make_planes(synth.SMALL.with_n(n), stride=stride))[0]
     dev = torch.device("cuda:0")
     pl = torch.from_numpy(planes).to(dev)
     keep_np = (np.random.default_rng(n + stride).random(n) < 0.45).astype(np.uint8)
@@ -147,7 +192,7 @@ def test_mixed_compact_kernels(n, stride, mask_offset, even_out, cap_frac):
     cap = int(sel.size * cap_frac)
     out_stride = cap + 2 + ((cap + (0 if even_out else 1)) % 2)
     assert (out_stride % 2 == 0) == even_out
-    out = torch.full((59, out_stride), -12345, dtype=torch.int16, device=dev)
+    out = torch.full((59, out_stride), -12345, dtype=torch.int16, device=dev).view(pl.dtype)
     idx = torch.full((out_stride,), -7, dtype=torch.int32, device=dev)
     nout = torch.empty(1, dtype=torch.int64, device=dev)
     ws = api.workspace(n, 1, dev)
@@ -156,6 +201,6 @@ def test_mixed_compact_kernels(n, stride, mask_offset, even_out, cap_frac):
     torch.cuda.synchronize()
     assert int(nout.item()) == sel.size
     o = out.cpu().numpy()
-    np.testing.assert_array_equal(o[:, :cap], planes[:, sel[:cap]])
+    np.testing.assert_array_equal(o[:, :cap].view(np.int16), planes[:, sel[:cap]].view(np.int16))
     np.testing.assert_array_equal(idx.cpu().numpy()[:cap], sel[:cap])
-    assert np.all(o[:, cap:] == -12345) and np.all(idx.cpu().numpy()[cap:] == -7)
+    assert np.all(o[:, cap:].view(np.int16) == -12345) and np.all(idx.cpu().numpy()[cap:] == -7)

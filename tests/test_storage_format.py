@@ -48,3 +48,23 @@ def test_mixed_round_trip_and_plane_split():
     assert rel.max() <= 2.0 ** -8       # unit roundoff of an 8-bit significand
     # already representable values survive a second conversion unchanged
     np.testing.assert_array_equal(synth.quantize_bf16_f16(d), q)
+
+
+def test_half_format_round_trip():
+    """The half 2-byte format: every plane IEEE half (numpy's conversion,
+    checked against the two neighbouring halves in FP64), within half a unit
+    of an 11-bit significand of the FP32 value for the scene's normal-range
+    values."""
+    spec = synth.SMALL.with_n(3000)
+    planes = synth.make_planes(spec)
+    h = synth.quantize_f16(planes)
+    assert h.dtype == np.float16 and h.shape == planes.shape
+    d = synth.dequantize_f16(h)
+    x = planes.astype(np.float64)
+    lo = np.nextafter(h, np.float16(-np.inf)).astype(np.float64)
+    hi = np.nextafter(h, np.float16(np.inf)).astype(np.float64)
+    err = np.abs(d.astype(np.float64) - x)
+    assert np.all(err <= np.abs(lo - x)) and np.all(err <= np.abs(hi - x))   # nearest half
+    normal = np.abs(x) >= 2.0 ** -14
+    assert np.all(err[normal] <= 2.0 ** -11 * np.abs(x[normal]))
+    np.testing.assert_array_equal(synth.quantize_f16(d), h)
