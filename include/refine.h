@@ -117,6 +117,11 @@ typedef struct {
  *           choice, 1 or 2 views evaluated per iteration of the view loop (two
  *           independent evaluations interleaved; each primitive's sum still
  *           adds the views in increasing order)
+ *  waves_per_block
+ *           binned path only, never a change of results: 0 = the library's
+ *           choice (4), or 1, 2, 4 or 8 wave64s (primitive groups of 64 or
+ *           128) per block of the view loop; a block's waves share one LDS
+ *           copy of the camera constants
  *  score_kind
  *           REFINE_SCORE_IMPORTANCE (0): the importance score of Eq. 7 with
  *           the Hessian weights of Eq. 20 (every switch above applies);
@@ -140,6 +145,7 @@ typedef struct {
     int32_t records_per_lane;
     int32_t views_per_iteration;
     int32_t score_kind;
+    int32_t waves_per_block;
 } refine_params;
 
 typedef enum { REFINE_PATH_AUTO = 0, REFINE_PATH_DIRECT = 1, REFINE_PATH_BINNED = 2 } refine_score_path;
@@ -350,8 +356,19 @@ typedef struct {
 
 refine_status refine_prune_batch_workspace_size(const refine_prune_job* jobs, int32_t n_jobs,
                                                 const refine_params* params, size_t* bytes);
+
+/*
+ * h_staging (nullable): PINNED host memory (hipHostMalloc) of at least
+ * n_jobs * REFINE_BATCH_STAGING_BYTES_PER_JOB bytes, owned by the caller.
+ * The call writes the device job table there and copies it to the workspace
+ * asynchronously on `stream`, so the caller must leave the buffer untouched
+ * until the stream has passed this call (an event recorded after it has
+ * completed).  With NULL the table goes through pageable memory and the call
+ * returns only once the copy has been taken.
+ */
+#define REFINE_BATCH_STAGING_BYTES_PER_JOB 256
 refine_status refine_prune_batch(const refine_prune_job* jobs, int32_t n_jobs, const refine_params* params,
-                                 void* d_ws, size_t ws_bytes, void* stream);
+                                 void* d_ws, size_t ws_bytes, void* h_staging, size_t staging_bytes, void* stream);
 
 #ifdef __cplusplus
 }

@@ -30,6 +30,7 @@ EXPORTED = ("refine_version", "refine_status_string", "refine_params_default", "
             "refine_select", "refine_compact", "refine_prune_batch_workspace_size", "refine_prune_batch",
             "refine_stats_noalloc")
 STATS_NOALLOC_MAX_N = 67108864
+BATCH_STAGING_BYTES_PER_JOB = 256
 
 
 class Scene(ctypes.Structure):
@@ -43,7 +44,8 @@ class Params(ctypes.Structure):
                 ("proj_mode", ctypes.c_int32), ("vis_mode", ctypes.c_int32),
                 ("equal_lambda", ctypes.c_int32), ("n_sub_views", ctypes.c_int32),
                 ("score_path", ctypes.c_int32), ("records_per_lane", ctypes.c_int32),
-                ("views_per_iteration", ctypes.c_int32), ("score_kind", ctypes.c_int32)]
+                ("views_per_iteration", ctypes.c_int32), ("score_kind", ctypes.c_int32),
+                ("waves_per_block", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -111,6 +113,10 @@ def load():
     lib.refine_select.restype = i32
     lib.refine_compact.argtypes = [ctypes.POINTER(Scene), P, ctypes.POINTER(Scene), P, P, P, sz, P]
     lib.refine_compact.restype = i32
+    lib.refine_prune_batch_workspace_size.argtypes = [P, i32, ctypes.POINTER(Params), ctypes.POINTER(sz)]
+    lib.refine_prune_batch_workspace_size.restype = i32
+    lib.refine_prune_batch.argtypes = [P, i32, ctypes.POINTER(Params), P, sz, P, sz, P]
+    lib.refine_prune_batch.restype = i32
     _lib = lib
     return lib
 

@@ -23,7 +23,7 @@ __all__ = ["Params", "default_params", "workspace", "workspace_size", "prune_cou
            "refine_stats_noalloc",
            "refine_score", "refine_score_prepare", "refine_score_cameras", "refine_score_views", "refine_select",
            "refine_compact",
-           "refine_prune_batch", "stats_from_tensor", "prune", "prune_batch", "version"]
+           "refine_prune_batch", "batch_staging", "stats_from_tensor", "prune", "prune_batch", "version"]
 
 
 def version() -> str:
@@ -247,13 +247,25 @@ def batch_workspace_size(jobs, params: Optional[Params] = None) -> int:
     return int(out.value)
 
 
-def refine_prune_batch(jobs, ws: torch.Tensor, params: Optional[Params] = None, stream=None) -> None:
+def batch_staging(n_jobs: int) -> torch.Tensor:
+    """A pinned host buffer for refine_prune_batch's job table (n_jobs jobs)."""
+    return torch.empty(max(n_jobs, 1) * _lib.BATCH_STAGING_BYTES_PER_JOB, dtype=torch.uint8, pin_memory=True)
+
+
+def refine_prune_batch(jobs, ws: torch.Tensor, params: Optional[Params] = None, stream=None,
+                       staging: Optional[torch.Tensor] = None) -> None:
     """Enqueue the batched prune of ``jobs`` (dicts of tensors: planes, cams,
     ratio, stats, scores, keep, out, optional n, n_keep, capacity, index_map,
-    n_out) in one grouped launch per kernel."""
+    n_out) in one grouped launch per kernel.  ``staging`` (from
+    batch_staging) makes the job-table copy asynchronous; it must stay
+    untouched until the stream has passed this call."""
     arr = _batch_jobs(jobs)
+    if staging is not None and (staging.is_cuda or not staging.is_pinned()):
+        raise ValueError("staging must be a pinned host tensor (batch_staging)")
     check(_lib.load().refine_prune_batch(arr, len(jobs), ctypes.byref(params or default_params()), _ptr(ws),
-                                         ws.numel(), _stream_ptr(stream)), "refine_prune_batch")
+                                         ws.numel(), _ptr(staging),
+                                         staging.numel() if staging is not None else 0, _stream_ptr(stream)),
+          "refine_prune_batch")
 
 
 def prune_batch(scenes, cams, ratios, params: Optional[Params] = None, stream=None) -> list:
@@ -273,7 +285,9 @@ def prune_batch(scenes, cams, ratios, params: Optional[Params] = None, stream=No
                      "index_map": torch.empty(max(cap, 1), dtype=torch.int32, device=dev),
                      "n_out": torch.empty(1, dtype=torch.int64, device=dev)})
     ws = torch.empty(max(batch_workspace_size(jobs, params), 1), dtype=torch.uint8, device=scenes[0].device)
-    refine_prune_batch(jobs, ws, params, stream)
+    staging = batch_staging(len(jobs))
+    refine_prune_batch(jobs, ws, params, stream, staging=staging)
     for j in jobs:
         j["workspace"] = ws
+        j["staging"] = staging      # in use until the stream has passed the call
     return jobs

@@ -17,7 +17,7 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 // the Python binding mirrors these layouts (tests/test_abi.py checks the same sizes)
 static_assert(sizeof(refine_scene) == 32, "refine_scene layout");
-static_assert(sizeof(refine_params) == 80, "refine_params layout");
+static_assert(sizeof(refine_params) == 88, "refine_params layout");
 static_assert(sizeof(refine_stats_t) == 96, "refine_stats_t layout");
 
 bool finite(double x) { return std::isfinite(x); }
@@ -62,6 +62,8 @@ refine_status check_params(const refine_params* p)
     if (p->records_per_lane < 0 || p->records_per_lane > 2) return REFINE_E_INVALID;
     if (p->views_per_iteration < 0 || p->views_per_iteration > 2) return REFINE_E_INVALID;
     if (p->score_kind != REFINE_SCORE_IMPORTANCE && p->score_kind != REFINE_SCORE_OPACITY) return REFINE_E_INVALID;
+    const int32_t w = p->waves_per_block;
+    if (w != 0 && w != 1 && w != 2 && w != 4 && w != 8) return REFINE_E_INVALID;
     return REFINE_OK;
 }
 
@@ -393,17 +395,25 @@ refine_status refine_prune_batch_workspace_size(const refine_prune_job* jobs, in
     return batch_size(jobs, n_jobs, params, bytes);
 }
 
+static_assert(sizeof(BatchJob) <= REFINE_BATCH_STAGING_BYTES_PER_JOB, "staging bytes per job");
+
 refine_status refine_prune_batch(const refine_prune_job* jobs, int32_t n_jobs, const refine_params* params,
-                                 void* d_ws, size_t ws_bytes, void* stream)
+                                 void* d_ws, size_t ws_bytes, void* h_staging, size_t staging_bytes, void* stream)
 {
     size_t need = 0;
     refine_status s = batch_size(jobs, n_jobs, params, &need);
     if (s != REFINE_OK) return s;
     if (!d_ws || ws_bytes < need) return REFINE_E_WORKSPACE;
+    if (h_staging && staging_bytes < (size_t)n_jobs * REFINE_BATCH_STAGING_BYTES_PER_JOB) return REFINE_E_WORKSPACE;
+    if (reinterpret_cast<uintptr_t>(h_staging) % alignof(BatchJob)) return REFINE_E_INVALID;
     char* base = static_cast<char*>(d_ws);
     BatchJob* d_table = reinterpret_cast<BatchJob*>(base);
     size_t off = align_up(sizeof(BatchJob) * (size_t)n_jobs);
-    std::vector<BatchJob> table((size_t)n_jobs);
+    // the table is built in the caller's pinned buffer when there is one (an
+    // asynchronous copy), else in pageable memory (HIP takes the copy before
+    // hipMemcpyAsync returns)
+    std::vector<BatchJob> pageable(h_staging ? 0 : (size_t)n_jobs);
+    BatchJob* table = h_staging ? static_cast<BatchJob*>(h_staging) : pageable.data();
     int64_t tiles = 0, blocks = 0;
     for (int32_t k = 0; k < n_jobs; ++k) {
         const refine_prune_job& j = jobs[k];
@@ -456,8 +466,7 @@ refine_status refine_prune_batch(const refine_prune_job* jobs, int32_t n_jobs, c
     }
     if (tiles > INT32_MAX || blocks > INT32_MAX) return REFINE_E_UNSUPPORTED;
     hipStream_t strm = static_cast<hipStream_t>(stream);
-    if (hipMemcpyAsync(d_table, table.data(), sizeof(BatchJob) * table.size(), hipMemcpyHostToDevice, strm) !=
-        hipSuccess)
+    if (hipMemcpyAsync(d_table, table, sizeof(BatchJob) * (size_t)n_jobs, hipMemcpyHostToDevice, strm) != hipSuccess)
         return REFINE_E_HIP;
     if (launch_stats_batch(d_table, n_jobs, (int)tiles, *params, strm) != hipSuccess) return REFINE_E_HIP;
     if (launch_score_batch(d_table, n_jobs, (int)blocks, *params, strm) != hipSuccess) return REFINE_E_HIP;

@@ -868,9 +868,13 @@ __global__ __launch_bounds__(kBlock) void place_groups(const uint32_t* __restric
 // lane l holds records l, l + 64, ... of it) and evaluates every view its
 // mask keeps, in increasing view order, for all its records; VPI = 2 takes
 // two kept views per iteration (two independent evaluation chains to
-// interleave; the sums still add the views in order).
+// interleave; the sums still add the views in order).  A block is 1 to
+// kMaxLoopWaves waves, which share one LDS copy of the camera table.
+constexpr int kMaxLoopWaves = 8;
+constexpr int kDefaultLoopWaves = 4;
+
 template <int PROJ, int PPL, int VPI>
-__global__ __launch_bounds__(kBlock) void score_binned(const PrimRec* __restrict__ recs, int n,
+__global__ __launch_bounds__(64 * kMaxLoopWaves) void score_binned(const PrimRec* __restrict__ recs, int n,
                                                          const CamRec* __restrict__ cams,
                                                          const uint64_t* __restrict__ mask,
                                                          const int32_t* __restrict__ order, int ngroups, int nv,
@@ -881,7 +885,7 @@ __global__ __launch_bounds__(kBlock) void score_binned(const PrimRec* __restrict
     // wave-uniform values (readfirstlane tells the compiler so: the mask
     // words then come in through scalar loads and the loop over their bits
     // runs on the scalar unit)
-    const int w = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * kBlock + threadIdx.x) >> 6);
+    const int w = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * blockDim.x + threadIdx.x) >> 6);
     const bool active = w < ngroups;   // waves past the last group still help load the camera table
     const int G = active ? min(max(__builtin_amdgcn_readfirstlane(order[w]), 0), ngroups - 1) : 0;
     const int g0 = G * kGroup * PPL;
@@ -912,7 +916,7 @@ __global__ __launch_bounds__(kBlock) void score_binned(const PrimRec* __restrict
     for (int c0 = 0; c0 < nv; c0 += kViewChunk) {
         const int cn = min(kViewChunk, nv - c0);
         __syncthreads();   // the previous chunk's reads are done
-        for (int t = threadIdx.x; t < cn * kStageVec; t += kBlock)
+        for (int t = threadIdx.x; t < cn * kStageVec; t += blockDim.x)
             table[t] = reinterpret_cast<const float4*>(cams + c0 + t / kStageVec)[t % kStageVec];
         __syncthreads();
         for (int v0 = c0; v0 < c0 + cn; v0 += 64) {
@@ -1050,10 +1054,11 @@ void views_mode(const void* planes, int64_t stride, int n, const refine_params& 
     if (binned) {
         const int ppl = records_per_lane(prm);
         const int ng = (int)num_groups(n, kGroup * ppl);
-        const unsigned loop_blocks = (unsigned)num_groups(ng, kWaves);
+        const int waves = prm.waves_per_block > 0 ? prm.waves_per_block : kDefaultLoopWaves;
+        const unsigned loop_blocks = (unsigned)num_groups(ng, waves);
         const int vpi = prm.views_per_iteration > 0 ? prm.views_per_iteration : kDefaultVPI;
         auto loop = [&](auto kernel) {
-            hipLaunchKernelGGL(kernel, dim3(loop_blocks), dim3(kBlock), 0, stream, ws.recs, n, ws.cams, ws.gmask,
+            hipLaunchKernelGGL(kernel, dim3(loop_blocks), dim3(64 * waves), 0, stream, ws.recs, n, ws.cams, ws.gmask,
                                ws.gorder, ng, nv, eta, zn, d_scores, evaluated);
         };
         if (ppl == 2)

@@ -25,8 +25,9 @@ from the job's own camera set.  The server
   path (stats, prepare, views, select, compact) on the slot's stream;
 * packs small scenes: when two or more small jobs (default parameters, at
   most ``pack_max_n`` primitives) wait at the head of the queue, up to
-  ``max_pack`` of them go to one slot as one ``refine_prune_batch`` -- a
-  single grouped launch per kernel for all of them;
+  ``max_pack`` of them go to one slot as one ``refine_prune_batch`` -- one
+  grouped launch per kernel (13 in all) for all of them, its job table
+  copied from the slot's pinned staging buffer without blocking the host;
 * notices completions by polling an event recorded after each launch unit's
   last call, then frees the slot and the reservation and admits the next
   jobs.
@@ -38,8 +39,12 @@ gives bit-identical scores, mask and survivors alone and in the mix.
 
 ``Tuner`` picks, per (primitive count, view count) bucket, the execution
 choice of the view loop -- direct, or binned with one or two primitives per
-lane -- by timing each on a synthetic scene of the bucket's size; choices
-never change results, only speed, and the table can be saved and reloaded.
+lane, one or two views per iteration and 2, 4 or 8 waves (128 to 1024
+primitives) per block -- by timing, on a scene of the bucket's size, the
+calls the server makes for such a job: the camera tables and the view loop
+on a prepared scene, or statistics and the whole scoring otherwise.
+Choices never change results, only speed; the table can be saved and
+reloaded.
 """
 from __future__ import annotations
 
@@ -118,17 +123,18 @@ def bucket_of(n: int, n_views: int) -> tuple[int, int]:
 
 
 # execution choices of the view loop: (score_path, records_per_lane,
-# views_per_iteration) -- primitives per lane and views per iteration of the
-# binned loop, or the direct loop
-CANDIDATES = ((1, 0, 0), (2, 1, 1), (2, 2, 1), (2, 1, 2), (2, 2, 2))
+# views_per_iteration, waves_per_block) -- primitives per lane, views per
+# iteration and waves per block of the binned loop, or the direct loop
+CANDIDATES = ((1, 0, 0, 0),) + tuple((2, ppl, vpi, w) for ppl in (1, 2) for vpi in (1, 2) for w in (2, 4, 8))
 
 
 def apply_choice(prm, cand) -> None:
-    """Set a tuner choice (path, records per lane[, views per iteration])
-    on a params struct (choices saved before views per iteration was tuned
-    have two entries)."""
+    """Set a tuner choice (path, records per lane[, views per iteration[,
+    waves per block]]) on a params struct (tables saved before the later
+    entries were tuned have fewer)."""
     prm.score_path, prm.records_per_lane = cand[0], cand[1]
     prm.views_per_iteration = cand[2] if len(cand) > 2 else 0
+    prm.waves_per_block = cand[3] if len(cand) > 3 else 0
 
 
 class Tuner:
@@ -150,10 +156,15 @@ class Tuner:
             raw = json.load(f)
         return cls({tuple(int(x) for x in k.split(",")): tuple(v) for k, v in raw.items()})
 
-    def tune(self, planes, cams_for_views, buckets, reps: int = 3, stream=None, log=None) -> None:
+    def tune(self, planes, cams_for_views, buckets, reps: int = 3, stream=None, log=None,
+             prepared: bool = True) -> None:
         """Time every candidate on prefixes of `planes` (a resident scene
         tensor at least as large as the biggest bucket) with camera sets from
-        `cams_for_views(V)`, keep the fastest per bucket."""
+        `cams_for_views(V)`, keep the fastest per bucket.  With `prepared`
+        (a server that prepares its scenes) a candidate is timed on what a
+        job on a prepared scene runs, the camera tables (with the culling and
+        group order) and the view loop; otherwise on the statistics and the
+        whole scoring a job runs from scratch."""
         import torch
 
         from . import _lib, api
@@ -166,6 +177,11 @@ class Tuner:
             ws = api.workspace(n, V, dev)
             st = torch.empty(_lib.STATS_BYTES, dtype=torch.uint8, device=dev)
             scores = torch.empty(n, dtype=torch.float32, device=dev)
+            if prepared:   # the scene as Server._prepare leaves it
+                prm0 = _lib.default_params()
+                prm0.score_path = _lib.PATH_BINNED
+                api.refine_stats(planes, st, ws, prm0, n=n, stream=s)
+                api.refine_score_prepare(planes, cams, st, ws, prm0, n=n, stream=s)
             best = None
             for cand in CANDIDATES:
                 prm = _lib.default_params()
@@ -174,8 +190,12 @@ class Tuner:
                 for r in range(reps + 1):
                     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                     e0.record(s)
-                    api.refine_stats(planes, st, ws, prm, n=n, stream=s)
-                    api.refine_score(planes, cams, st, scores, ws, prm, n=n, stream=s)
+                    if prepared:
+                        api.refine_score_cameras(planes, cams, ws, prm, n=n, stream=s)
+                        api.refine_score_views(planes, V, st, scores, ws, prm, n=n, stream=s)
+                    else:
+                        api.refine_stats(planes, st, ws, prm, n=n, stream=s)
+                        api.refine_score(planes, cams, st, scores, ws, prm, n=n, stream=s)
                     e1.record(s)
                     e1.synchronize()
                     if r:
@@ -186,7 +206,7 @@ class Tuner:
             self.table[(lb_n, lb_v)] = best[1]
             if log:
                 log(f"tuner: bucket n=2^{lb_n} V=2^{lb_v} -> path {best[1][0]} ppl {best[1][1]} vpi {best[1][2]} "
-                    f"({best[0]:.3f} ms)")
+                    f"waves {best[1][3]} ({best[0]:.3f} ms)")
 
 
 # ------------------------------------------------------------------ server
@@ -256,6 +276,10 @@ class Server:
         self.max_pack = int(max_pack)
         self.tuner = tuner
         self._next_id = 0
+        # per slot: the pinned host buffer a packed launch's job table is
+        # copied from (a slot's next launch waits for its previous one to end)
+        from . import api
+        self.staging = [api.batch_staging(self.max_pack) for _ in range(slots)]
 
     def _budget(self) -> int:
         if self.explicit_budget is not None:
@@ -410,7 +434,7 @@ class Server:
         s.wait_stream(torch.cuda.current_stream(dev))
         start = torch.cuda.Event(enable_timing=True)
         start.record(s)
-        api.refine_prune_batch(descs, ws, prm, stream=s)
+        api.refine_prune_batch(descs, ws, prm, stream=s, staging=self.staging[slot])
         done = torch.cuda.Event(enable_timing=True)
         done.record(s)
         now = time.perf_counter()

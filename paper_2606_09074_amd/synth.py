@@ -271,11 +271,12 @@ SERVE_RATE = 20.0
 
 
 def serve_scene_specs(count: int, seed: int = 3000, n_range=SERVE_N_RANGE) -> list:
-    """Specs of `count` resident scenes whose primitive counts stratify the
-    log-uniform law on n_range (the midpoints of `count` equal-probability
-    strata), so jobs that pick a scene uniformly see that law."""
+    """Specs of `count` resident scenes whose primitive counts are evenly
+    spaced in log over n_range, both ends included (so the largest scene of
+    the law, which sets the tail latency, is served), and jobs that pick a
+    scene uniformly see a discretised log-uniform law."""
     lo, hi = np.log(n_range[0]), np.log(n_range[1])
-    ns = np.exp(lo + (np.arange(count) + 0.5) / count * (hi - lo)).astype(np.int64)
+    ns = np.round(np.exp(lo + np.arange(count) / max(count - 1, 1) * (hi - lo))).astype(np.int64)
     return [dataclasses.replace(SMALL, name=f"serve-{j}-{int(n)}", n=int(n), seed=seed + 1 + j)
             for j, n in enumerate(ns)]
 

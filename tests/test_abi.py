@@ -43,7 +43,7 @@ def test_every_declared_function_is_exported(lib):
 def test_struct_sizes_match_header():
     from paper_2606_09074_amd import _lib
     assert ctypes.sizeof(_lib.Scene) == 32
-    assert ctypes.sizeof(_lib.Params) == 80
+    assert ctypes.sizeof(_lib.Params) == 88
     assert ctypes.sizeof(_lib.Stats) == 96
 
 
@@ -119,7 +119,8 @@ def test_stats_validation(lib):
     for field, bad in (("eta", 0.0), ("eta", float("nan")), ("z_near", -1.0), ("clamp_k", 0.0),
                        ("e_col", 0.0), ("e_lngem", float("inf")), ("proj_mode", 3), ("vis_mode", -1),
                        ("equal_lambda", 2), ("n_sub_views", -5), ("score_path", 3), ("records_per_lane", 3),
-                       ("records_per_lane", -1), ("views_per_iteration", 3), ("views_per_iteration", -1)):
+                       ("records_per_lane", -1), ("views_per_iteration", 3), ("views_per_iteration", -1),
+                       ("waves_per_block", 3), ("waves_per_block", 16), ("waves_per_block", -1), ("score_kind", 2)):
         q = _lib.default_params()
         setattr(q, field, bad)
         assert call(_scene(), prm=q) == E, field
@@ -228,9 +229,9 @@ def test_batch_validation(lib):
         out = ctypes.c_size_t(0)
         return lib.refine_prune_batch_workspace_size(arr, len(jobs), ctypes.byref(prm), ctypes.byref(out)), out.value
 
-    def run(*jobs, wsb=1 << 30, ws=FAKE):
+    def run(*jobs, wsb=1 << 30, ws=FAKE, staging=None, stb=0):
         arr = (_lib.PruneJob * len(jobs))(*jobs)
-        return lib.refine_prune_batch(arr, len(jobs), ctypes.byref(p), ws, wsb, None)
+        return lib.refine_prune_batch(arr, len(jobs), ctypes.byref(p), ws, wsb, staging, stb, None)
     rc, b1 = size(job())
     assert rc == 0 and b1 > 0
     rc, b2 = size(job(), job(n=5000))
@@ -245,6 +246,9 @@ def test_batch_validation(lib):
     assert size(job(n=4096 * 4096 + 1))[0] == U
     assert run(job(), wsb=b1 - 1) == W
     assert run(job(), ws=0) == W
+    # a staging buffer too small for the job table, or misaligned, is refused before any copy
+    assert run(job(), job(), staging=FAKE, stb=_lib.BATCH_STAGING_BYTES_PER_JOB) == W
+    assert run(job(), staging=FAKE + 4, stb=_lib.BATCH_STAGING_BYTES_PER_JOB) == E
 
 
 def test_stats_noalloc_validation(lib):

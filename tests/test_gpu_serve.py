@@ -1,6 +1,8 @@
 """The serving loop on the GPU: each job's results are the same alone and in
-the mix (overlapping on several streams), admission respects the memory
-budget, and the tuner's choices leave results unchanged."""
+the mix (overlapping on several streams) and match the FP64 oracle (scores
+within tolerance, masks except borderline primitives, survivors bit-exact),
+admission respects the memory budget, and the tuner's choices leave results
+unchanged."""
 import numpy as np
 import pytest
 
@@ -15,21 +17,27 @@ def pool():
     import torch
     assert torch.cuda.is_available(), "GPU tests need a GPU"
     dev = torch.device("cuda:0")
-    specs = synth.serve_scene_specs(4, seed=77, n_range=(20_000, 400_000))
-    scenes = []
+    specs = synth.serve_scene_specs(5, seed=77, n_range=(20_000, 400_000))
+    scenes, host = [], []
     for j, sp in enumerate(specs):
         pl = synth.make_planes(sp)
-        if j == 2:                                    # one resident scene in 2-byte storage
+        if j == 2:                                    # resident scenes in the two 2-byte storages
             pl = synth.quantize_bf16_f16(pl)
+            host.append(synth.dequantize_bf16_f16(pl))
+        elif j == 3:
+            pl = synth.quantize_f16(pl)
+            host.append(synth.dequantize_f16(pl))
+        else:
+            host.append(pl)
         scenes.append(torch.from_numpy(pl).to(dev))
-    arr, jobs = synth.serve_requests(14, n_scenes=len(scenes), seed=78, views_range=(16, 120))
+    arr, jobs = synth.serve_requests(16, n_scenes=len(scenes), seed=78, views_range=(16, 120))
     cams = {}
     for _, V, _ in jobs:
         if V not in cams:
             cams[V] = torch.from_numpy(synth.ring_cameras(V)).to(dev)
     torch.cuda.synchronize()
     log(f"serve pool: n={[s.shape[1] for s in scenes]} jobs={jobs}")
-    return scenes, jobs, cams
+    return scenes, jobs, cams, host
 
 
 def _results(job):
@@ -55,7 +63,7 @@ def test_results_same_alone_and_in_the_mix(pool, packing):
     without packing, scenes prepared once and jobs only rebuild camera
     tables; with packing, the small jobs share grouped launches.  Results
     must be identical."""
-    scenes, jobs, cams = pool
+    scenes, jobs, cams, host = pool
     alone = []
     srv1 = _server(scenes, slots=1, prepare_scenes=False, pack_max_n=0)
     srv1_jobs = []
@@ -84,11 +92,26 @@ def test_results_same_alone_and_in_the_mix(pool, packing):
         assert a[4] == b[4] == j.n_keep
     log(f"[serve packing={packing}] {len(jobs)} jobs identical alone and mixed; peak units in flight {peak}, "
         f"largest unit {largest_unit} jobs")
+    # every served job against the FP64 oracle on its scene (dequantised for
+    # 2-byte storage) and its own camera set
+    import oracle
+    from tests.gpu_common import check_mask_vs_oracle, check_scores, oracle_all
+    for j, (sc, V, r) in zip(subm, jobs):
+        scores, keep, out, index_map, n_out = _results(j)
+        F, lam, D, lo, hi = oracle_all(host[sc], synth.ring_cameras(V))
+        check_scores(scores.view(np.float32), D, lo, hi, f"served job {j.id} scene {sc} V={V}")
+        n_prune = oracle.n_prune(j.n, r)
+        check_mask_vs_oracle(keep, D, lo, hi, n_prune, f"served job {j.id} mask")
+        stored = scenes[sc][:, :j.n].cpu().numpy()
+        bits = np.uint32 if stored.dtype == np.float32 else np.uint16
+        sel = np.nonzero(keep)[0]
+        np.testing.assert_array_equal(out.view(bits), stored[:, sel].view(bits))
+        np.testing.assert_array_equal(index_map, sel.astype(np.int32))
 
 
 def test_admission_budget_bounds_memory(pool):
     from paper_2606_09074_amd import api, serve
-    scenes, jobs, cams = pool
+    scenes, jobs, cams, _ = pool
     sizes = []
     for sc, V, r in jobs:
         n = scenes[sc].shape[1]
@@ -109,19 +132,23 @@ def test_admission_budget_bounds_memory(pool):
         small.submit(0, cams[jobs[0][1]], 0.5)
 
 
-def test_tuner_choices_do_not_change_results(pool):
+@pytest.mark.parametrize("prepared", [True, False])
+def test_tuner_choices_do_not_change_results(pool, prepared):
+    """The tuner times the calls the server makes (camera tables and view
+    loop on prepared scenes, or the whole scoring); whatever it picks, the
+    served results are those of the default choices."""
     import torch
 
     from paper_2606_09074_amd import serve
-    scenes, jobs, cams = pool
+    scenes, jobs, cams, _ = pool
     big = max(scenes, key=lambda s: s.shape[1] if s.dtype == torch.float32 else 0)
     tuner = serve.Tuner()
     tuner.tune(big, lambda V: torch.from_numpy(synth.ring_cameras(V)).to(big.device),
-               buckets=[(15, 5), (18, 6)], reps=2, log=log)
+               buckets=[(15, 5), (18, 6)], reps=2, log=log, prepared=prepared)
     assert set(tuner.table) == {(15, 5), (18, 6)}
     assert all(c in serve.CANDIDATES for c in tuner.table.values())
-    tuned = _server(scenes, slots=2, tuner=tuner)
-    plain = _server(scenes, slots=2)
+    tuned = _server(scenes, slots=2, tuner=tuner, prepare_scenes=prepared)
+    plain = _server(scenes, slots=2, prepare_scenes=prepared)
     for sc, V, r in jobs[:6]:
         a = tuned.submit(sc, cams[V], r)
         b = plain.submit(sc, cams[V], r)
