@@ -10,9 +10,13 @@ resident in HBM before timing starts.  Prints ONE JSON line.
 
 value = Gaussian-view evaluations per second of the whole step
 (N * |V| / step time); ms_per_step is the time of one 3M-Gaussian prune.
-The roofline object describes refine_score (the dominant launch), timed
-with HIP events on its own stream over the timed region.  cpu_baseline
-times the FP64 CPU oracle on the host's cores on the same workload.
+The roofline object describes the view loop (the dominant kernel, the one
+launch of refine_score_views), timed with HIP events on its launch stream in
+every timed step.  cpu_baseline times the FP64 CPU oracle on the host's
+cores on the same workload (all threads, and one thread on a sample);
+precision reports each 2-byte storage's prune time and its error against
+that oracle; other_workloads the small (50k x 16) and large (6M x 300)
+prunes; serving the served latencies (paper_2606_09074_amd.serve).
 """
 from __future__ import annotations
 
@@ -26,10 +30,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# Algorithmic work of the scoring, per (primitive, view) pair and per
-# primitive (FLOP; FMA = 2, mul/add/rcp/sqrt = 1, compares/min/max = 0), and
-# bytes per primitive (14 fp32 attribute planes read, one fp32 score written).
-FLOP_PER_PAIR = {0: 103, 1: 25, 2: 22}
+# Algorithmic work of the scoring per (primitive, view) pair (FLOP; FMA = 2,
+# mul/add/rcp/sqrt = 1, compares/min/max = 0), from the per-pair ledger of
+# the projected-covariance evaluation: transform 18, reciprocal 1, x/z and
+# y/z 2, u and v 4, Jacobian 4, J R_v 18, (J R_v) L 30, a b c 15, largest
+# eigenvalue and radius 11, footprint box 4, projection term 6, accumulate 1
+# = 114 (the kernel's square-root-free gate executes a few less).  DEPTH
+# and NONE modes skip the covariance part.
+FLOP_PER_PAIR = {0: 114, 1: 25, 2: 22}
 # a pair screened out after its first step: camera-space centre 18, d z 4, bound 1
 FLOP_PER_SCREENED_PAIR = 23
 BYTES_PER_PRIM = 14 * 4 + 4
@@ -98,9 +106,14 @@ def main() -> int:
                     help="binned records each lane of the view loop holds (0: the library's default)")
     ap.add_argument("--views-per-iteration", type=int, default=0, choices=[0, 1, 2],
                     help="views the binned view loop evaluates per iteration (0: the library's default)")
-    ap.add_argument("--storage", default="f32", choices=["f32", "bf16-f16"],
-                    help="scene storage: FP32 planes, or BF16 geometry/opacity + FP16 SH (arithmetic is FP32 either way)")
+    ap.add_argument("--waves-per-block", type=int, default=0, choices=[0, 1, 2, 4, 8],
+                    help="waves per block of the binned view loop (0: the library's default)")
+    ap.add_argument("--storage", default="f32", choices=["f32", "bf16-f16", "f16"],
+                    help="scene storage: FP32 planes, BF16 geometry/opacity + FP16 SH, or FP16 throughout "
+                         "(arithmetic is FP32 either way)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-other-workloads", action="store_true",
+                    help="skip the prune times of the small and large workloads")
     ap.add_argument("--serve-jobs", type=int, default=240,
                     help="prune jobs per storage format in the served-latency run (0: skip it)")
     ap.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrival rate of the served jobs (1/s)")
@@ -111,15 +124,13 @@ def main() -> int:
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(f"bench.py measures one GPU: this build runs the path on a single MI355X "
-              f"(--gpus {args.gpus} requested); the multi-GPU sharding is described in DESIGN.md",
-              file=sys.stderr)
+        print(f"bench.py measures one GPU: the path runs on a single MI355X (--gpus {args.gpus} requested); "
+              f"sharding over several GPUs is a design that is not built", file=sys.stderr)
         return 2
 
-    import numpy as np
     import torch
 
-    from paper_2606_09074_amd import _lib, api, synth
+    from paper_2606_09074_amd import _lib, synth
 
     _lib.load()
     if not torch.cuda.is_available():
@@ -139,93 +150,31 @@ def main() -> int:
     log(f"bench: generating {spec.name} (n={spec.n}, V={spec.n_views}), ratio {ratio}")
     planes_np = synth.make_planes(spec)
     cams_np = synth.make_cameras(spec)
-    if args.storage == "bf16-f16":
-        stored_np = synth.quantize_bf16_f16(planes_np)
-        planes_np = synth.dequantize_bf16_f16(stored_np)   # the values the 2-byte scene holds
-    else:
-        stored_np = planes_np
+    stored_np = STORAGES[args.storage][0](planes_np)
+    planes_np = STORAGES[args.storage][1](stored_np)   # the values the scene holds
     n, V = spec.n, cams_np.shape[0]
     dev = torch.device("cuda:0")
-    stream = torch.cuda.current_stream(dev)
-    planes = torch.from_numpy(stored_np).to(dev)
-    cams = torch.from_numpy(cams_np).to(dev)
     params = _lib.default_params()
     params.score_path = {"auto": _lib.PATH_AUTO, "direct": _lib.PATH_DIRECT, "binned": _lib.PATH_BINNED}[args.score_path]
     params.records_per_lane = args.records_per_lane
     params.views_per_iteration = args.views_per_iteration
-    ws = api.workspace(n, V, dev)
-    st = torch.empty(_lib.STATS_BYTES, dtype=torch.uint8, device=dev)
-    scores = torch.empty(n, dtype=torch.float32, device=dev)
-    keep = torch.empty(n, dtype=torch.uint8, device=dev)
-    n_keep = torch.empty(1, dtype=torch.int64, device=dev)
-    cap = n - api.prune_count(n, ratio)
-    out = torch.empty((59, max(cap, 1)), dtype=planes.dtype, device=dev)
-    idx = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
-    torch.cuda.synchronize()
-
-    phases = ("stats", "prepare", "views", "select", "compact")
-    n_ev = max(args.steps, 1)
-    ev = {k: [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n_ev)]
-          for k in phases}
-
-    def step(j: int | None, marked=("views",)):
-        def mark(k, e):
-            if j is not None and k in marked:
-                ev[k][j][e].record(stream)
-        mark("stats", 0)
-        api.refine_stats(planes, st, ws, params, stream=stream)
-        mark("stats", 1)
-        mark("prepare", 0)
-        api.refine_score_prepare(planes, cams, st, ws, params, stream=stream)
-        mark("prepare", 1)
-        mark("views", 0)
-        api.refine_score_views(planes, V, st, scores, ws, params, stream=stream)
-        mark("views", 1)
-        mark("select", 0)
-        api.refine_select(scores, keep, ws, ratio=ratio, n_keep_out=n_keep, stream=stream)
-        mark("select", 1)
-        mark("compact", 0)
-        api.refine_compact(planes, keep, out, ws, index_map_out=idx, capacity=cap, stream=stream)
-        mark("compact", 1)
-
-    for _ in range(args.warmup):
-        step(None)
-    torch.cuda.synchronize()
-    log(f"bench: warmup done ({args.warmup} steps); timing {args.steps} steps")
-
-    # timed region: wall clock around K steps; HIP events on the launch stream
-    # bracket the view loop (the dominant kernel) in every step
-    t0 = time.perf_counter()
-    for j in range(args.steps):
-        step(j)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    views_ms = [a.elapsed_time(b) for a, b in ev["views"][:args.steps]]
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    params.waves_per_block = args.waves_per_block
+    run = Pruner(torch.from_numpy(stored_np).to(dev), torch.from_numpy(cams_np).to(dev), ratio, params)
+    res = run.time(args.steps, args.warmup)
+    ms_per_step = res["ms_per_step"]
     value = n * V / (ms_per_step / 1e3)
-
-    # per-phase breakdown from a separate, untimed pass with events around every call
-    for j in range(args.steps):
-        step(j, marked=phases)
-    torch.cuda.synchronize()
-    avg = {k: float(np.mean([a.elapsed_time(b) for a, b in ev[k][:args.steps]])) for k in phases}
-    avg["views"] = float(np.mean(views_ms))
+    avg = res["phases_ms"]
     log(f"bench: {ms_per_step:.3f} ms/step, phases {avg}")
+    n_eval, n_screened = run.pair_counts()
 
-    # pairs the view loop evaluated in full, and pairs it screened out after
-    # their first step (culled pairs are in neither), read once after the timed region
-    evaluated = torch.zeros(2, dtype=torch.int64, device=dev)
-    api.refine_score_views(planes, V, st, scores, ws, params, evaluated_out=evaluated, stream=stream)
-    torch.cuda.synchronize()
-    n_eval, n_screened = (int(x) for x in evaluated.cpu().tolist())
-
-    # roofline of the view loop (the dominant kernel): ALU-bound FP32 work it
-    # actually performed, over its event-timed duration
+    # roofline of the view loop (the dominant kernel, the only launch of
+    # refine_score_views): FP32 work it performed, over its event-timed
+    # duration on the launch stream
     t_views = avg["views"] / 1e3
     flops = FLOP_PER_PAIR[params.proj_mode] * n_eval + FLOP_PER_SCREENED_PAIR * n_screened
     achieved_tflops = flops / t_views / 1e12
     kname = "score_binned" if n_eval < n * V else "score_direct"
-    counters = profiled_counters(kname, spec.name) if params.proj_mode == 0 else {}
+    counters = profiled_counters(kname, spec.name) if (params.proj_mode == 0 and args.storage == "f32") else {}
     traffic = counters.get("hbm_bytes_per_launch")
     valu = counters.get("valu_insts_per_launch")
     valu_issue = None
@@ -239,22 +188,42 @@ def main() -> int:
                 "flop_per_pair": FLOP_PER_PAIR[params.proj_mode], "pairs_evaluated": n_eval,
                 "flop_per_screened_pair": FLOP_PER_SCREENED_PAIR, "pairs_screened": n_screened,
                 "pairs_total": n * V, "views_ms": round(avg["views"], 4), "prepare_ms": round(avg["prepare"], 4)}
+
+    # the other workloads: the small one (50k x 16, launch-bound) and the
+    # large one (6M x 300), same path and parameters
+    others = {}
+    if not args.no_other_workloads:
+        for name in ("small", "large"):
+            if name == args.workload:
+                continue
+            sp = synth.SPECS[name]
+            log(f"bench: {sp.name}")
+            pr = Pruner(torch.from_numpy(STORAGES[args.storage][0](synth.make_planes(sp))).to(dev),
+                        torch.from_numpy(synth.make_cameras(sp)).to(dev), sp.ratios[0], params)
+            r = pr.time(args.steps, args.warmup)
+            others[sp.name] = {"ms_per_prune": r["ms_per_step"], "ratio": sp.ratios[0],
+                               "evals_per_s": round(sp.n * sp.n_views / (r["ms_per_step"] / 1e3), 1),
+                               "phases_ms": r["phases_ms"]}
+            del pr
+            torch.cuda.empty_cache()
+
     cpu = None
+    precision = None
     if not args.no_cpu_baseline:
-        import oracle
-        log("bench: timing the FP64 CPU oracle on the same workload")
-        oracle.build(force=False)
-        prm = oracle.Params()
-        tc0 = time.perf_counter()
-        F = oracle.stats(planes_np, eta=prm.eta)
-        lam = oracle.lam(F, prm)
-        D, _, _, _ = oracle.score(planes_np, cams_np, lam, prm)
-        keep_o, _ = oracle.select(D, oracle.n_prune(n, ratio))
-        oracle.compact(planes_np, keep_o)
-        tc = time.perf_counter() - tc0
-        cpu = {"value": round(n * V / tc, 1), "unit": "evals/s", "cores": oracle.num_threads(), "kind": "oracle",
-               "sample": f"full {spec.name} prune (stats+score+select+compact), {tc:.2f} s",
-               "ms_per_prune": round(tc * 1e3, 1)}
+        cpu, D_oracle = cpu_baseline(spec, planes_np, cams_np, ratio)
+        # each 2-byte storage of this workload: its prune time, and its
+        # scores and kept sets against the FP64 oracle on the FP32 scene
+        if args.storage == "f32" and args.workload == "medium":
+            precision = {}
+            for st_name in ("bf16-f16", "f16"):
+                q = STORAGES[st_name][0](planes_np)
+                pr = Pruner(torch.from_numpy(q).to(dev), run.cams, ratio, params)
+                r = pr.time(args.steps, args.warmup)
+                precision[st_name] = {"ms_per_prune": r["ms_per_step"], "phases_ms": r["phases_ms"],
+                                      **storage_error(pr.score_only(), D_oracle, spec.n)}
+                del pr
+                torch.cuda.empty_cache()
+            precision["f32"] = storage_error(run.score_only(), D_oracle, spec.n)
 
     serving = serve_bench(args) if args.serve_jobs > 0 else None
 
@@ -263,21 +232,209 @@ def main() -> int:
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
             "data": "synthetic",
             "config": {"workload": spec.name, "n": n, "views": V, "ratio": ratio, "storage": args.storage,
-                       "step": "stats+score+select+compact", "score_path": args.score_path, "records_per_lane": args.records_per_lane,
-                       "views_per_iteration": args.views_per_iteration,
-                       "ms_per_prune": round(ms_per_step, 4)},
+                       "step": "stats+score+select+compact", "score_path": args.score_path,
+                       "records_per_lane": args.records_per_lane, "views_per_iteration": args.views_per_iteration,
+                       "waves_per_block": args.waves_per_block, "ms_per_prune": round(ms_per_step, 4)},
             "phases_ms": {k: round(v, 4) for k, v in avg.items()},
-            "roofline": roofline, "cpu_baseline": cpu, "serving": serving}
+            "roofline": roofline, "cpu_baseline": cpu, "precision": precision, "other_workloads": others,
+            "serving": serving}
     print(json.dumps(line), flush=True)
     return 0
 
 
+def _identity(x):
+    return x
+
+
+def _storages():
+    from paper_2606_09074_amd import synth
+    return {"f32": (_identity, _identity),
+            "bf16-f16": (synth.quantize_bf16_f16, synth.dequantize_bf16_f16),
+            "f16": (synth.quantize_f16, synth.dequantize_f16)}
+
+
+class _LazyStorages(dict):
+    def __missing__(self, key):
+        self.update(_storages())
+        return dict.__getitem__(self, key)
+
+
+STORAGES = _LazyStorages()
+
+
+class Pruner:
+    """One resident scene and its buffers: times whole prune steps (stats ->
+    prepare -> views -> select -> compact on one stream, inputs in HBM)."""
+
+    PHASES = ("stats", "prepare", "views", "select", "compact")
+
+    def __init__(self, planes, cams, ratio, params):
+        import torch
+
+        from paper_2606_09074_amd import _lib, api
+        self.torch, self.api = torch, api
+        self.planes, self.cams, self.ratio, self.params = planes, cams, ratio, params
+        dev = planes.device
+        self.n, self.V = planes.shape[1], cams.shape[0]
+        self.stream = torch.cuda.current_stream(dev)
+        self.ws = api.workspace(self.n, self.V, dev)
+        self.st = torch.empty(_lib.STATS_BYTES, dtype=torch.uint8, device=dev)
+        self.scores = torch.empty(self.n, dtype=torch.float32, device=dev)
+        self.keep = torch.empty(self.n, dtype=torch.uint8, device=dev)
+        self.n_keep = torch.empty(1, dtype=torch.int64, device=dev)
+        self.cap = self.n - api.prune_count(self.n, ratio)
+        self.out = torch.empty((59, max(self.cap, 1)), dtype=planes.dtype, device=dev)
+        self.idx = torch.empty(max(self.cap, 1), dtype=torch.int32, device=dev)
+        torch.cuda.synchronize()
+
+    def step(self, ev=None, j=0, marked=("views",)):
+        api, s, prm = self.api, self.stream, self.params
+
+        def mark(k, e):
+            if ev is not None and k in marked:
+                ev[k][j][e].record(s)
+        mark("stats", 0)
+        api.refine_stats(self.planes, self.st, self.ws, prm, stream=s)
+        mark("stats", 1)
+        mark("prepare", 0)
+        api.refine_score_prepare(self.planes, self.cams, self.st, self.ws, prm, stream=s)
+        mark("prepare", 1)
+        mark("views", 0)
+        api.refine_score_views(self.planes, self.V, self.st, self.scores, self.ws, prm, stream=s)
+        mark("views", 1)
+        mark("select", 0)
+        api.refine_select(self.scores, self.keep, self.ws, ratio=self.ratio, n_keep_out=self.n_keep, stream=s)
+        mark("select", 1)
+        mark("compact", 0)
+        api.refine_compact(self.planes, self.keep, self.out, self.ws, index_map_out=self.idx, capacity=self.cap,
+                           stream=s)
+        mark("compact", 1)
+
+    def time(self, steps, warmup) -> dict:
+        """K timed steps bracketed by synchronisations (wall clock), with HIP
+        events on the launch stream around every view loop; then the same
+        number of untimed steps with events around every phase."""
+        import numpy as np
+        torch = self.torch
+        n_ev = max(steps, 1)
+        ev = {k: [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n_ev)]
+              for k in self.PHASES}
+        for _ in range(warmup):
+            self.step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for j in range(steps):
+            self.step(ev, j)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        views_ms = [a.elapsed_time(b) for a, b in ev["views"][:steps]]
+        for j in range(steps):
+            self.step(ev, j, marked=self.PHASES)
+        torch.cuda.synchronize()
+        avg = {k: float(np.mean([a.elapsed_time(b) for a, b in ev[k][:steps]])) for k in self.PHASES}
+        avg["views"] = float(np.mean(views_ms))
+        return {"ms_per_step": round((t1 - t0) * 1e3 / max(steps, 1), 4), "phases_ms": {k: round(v, 4) for k, v in avg.items()}}
+
+    def pair_counts(self):
+        """Pairs the view loop evaluated in full and pairs it screened out
+        after their first step (culled pairs are in neither)."""
+        torch = self.torch
+        evaluated = torch.zeros(2, dtype=torch.int64, device=self.planes.device)
+        self.api.refine_score_views(self.planes, self.V, self.st, self.scores, self.ws, self.params,
+                                    evaluated_out=evaluated, stream=self.stream)
+        torch.cuda.synchronize()
+        return tuple(int(x) for x in evaluated.cpu().tolist())
+
+    def score_only(self):
+        """Scores of one step, on the host."""
+        self.step()
+        self.torch.cuda.synchronize()
+        return self.scores.cpu().numpy().copy()
+
+
+def storage_error(scores, D, n) -> dict:
+    """Score relative error and kept-set Jaccard at beta 0.5 and 0.9 of GPU
+    scores against the FP64 oracle's scores of the FP32 scene (ranking by
+    (score, index), as the library's selection does)."""
+    import numpy as np
+    s = scores.astype(np.float64)
+    nz = D > 0
+    rel = np.abs(s[nz] - D[nz]) / D[nz]
+    out = {"score_rel_err_median": float(np.median(rel)), "score_rel_err_p99": float(np.quantile(rel, 0.99))}
+    idx = np.arange(n)
+    for beta in (0.5, 0.9):
+        k = int(np.floor(beta * n + 0.5))
+        ka = np.ones(n, bool)
+        ka[np.lexsort((idx, scores.astype(np.float32)))[:k]] = False
+        kb = np.ones(n, bool)
+        kb[np.lexsort((idx, D))[:k]] = False
+        out[f"jaccard_vs_oracle_{beta}"] = round(float((ka & kb).sum()) / float((ka | kb).sum()), 6)
+    return {k: (round(v, 8) if isinstance(v, float) else v) for k, v in out.items()}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(spec, planes_np, cams_np, ratio):
+    """The FP64 oracle as it stands, timed on the host: the whole prune of
+    the workload on all its OpenMP threads, and one thread on a bounded
+    sample (every 8th primitive; the per-primitive work is independent, so
+    its rate is that of the whole).  Returns the baseline and the oracle's
+    scores (kept for the precision report)."""
+    import subprocess
+
+    import oracle
+    log("bench: timing the FP64 CPU oracle on the same workload")
+    oracle.build(force=False)
+    prm = oracle.Params()
+    n, V = planes_np.shape[1], cams_np.shape[0]
+    tc0 = time.perf_counter()
+    F = oracle.stats(planes_np, eta=prm.eta)
+    lam = oracle.lam(F, prm)
+    D, _, _, _ = oracle.score(planes_np, cams_np, lam, prm)
+    keep_o, _ = oracle.select(D, oracle.n_prune(n, ratio))
+    oracle.compact(planes_np, keep_o)
+    tc = time.perf_counter() - tc0
+    # one thread, in a child process (OMP_NUM_THREADS=1) that draws the same
+    # scene and times the oracle's scoring of every 8th primitive
+    code = ("import sys, time, numpy as np; sys.path.insert(0, %r); import oracle; "
+            "from paper_2606_09074_amd import synth; sp = synth.SPECS[%r]; pl = synth.make_planes(sp); "
+            "cm = synth.make_cameras(sp); prm = oracle.Params(); idx = np.arange(0, sp.n, 8); "
+            "t0 = time.perf_counter(); F = oracle.stats(pl, eta=prm.eta); lam = oracle.lam(F, prm); "
+            "oracle.score(pl, cm, lam, prm, idx=idx); print(time.perf_counter() - t0, idx.size, oracle.num_threads())"
+            ) % (ROOT, {"medium-3M-x200": "medium", "small-50k-x16": "small", "large-6M-x300": "large"}[spec.name])
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    single = None
+    try:
+        out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=300,
+                             check=True).stdout.split()
+        t1, m, thr = float(out[0]), int(out[1]), int(out[2])
+        single = {"value": round(m * V / t1, 1), "unit": "evals/s", "cores": thr,
+                  "sample": f"statistics of all {n} + scores of every 8th primitive ({m}) x {V} views, {t1:.2f} s"}
+    except (subprocess.SubprocessError, ValueError, IndexError) as e:
+        log(f"bench: single-thread oracle leg failed: {e}")
+    cpu = {"value": round(n * V / tc, 1), "unit": "evals/s", "cores": oracle.num_threads(), "kind": "oracle",
+           "sample": f"full {spec.name} prune (stats+score+select+compact), {tc:.2f} s",
+           "ms_per_prune": round(tc * 1e3, 1), "cpu_model": cpu_model(), "single_thread": single}
+    return cpu, D
+
+
 def serve_bench(args) -> dict:
     """Served latency: Poisson arrivals of prune jobs on resident, prepared
-    scenes (paper_2606_09074_amd.serve), once with FP32 scenes and once with
-    the same scenes in 2-byte storage, once more with FP32 scenes where every
-    job runs the whole path, then a burst of the same jobs with and without
-    overlap.  Latency = completion seen by the host - arrival time."""
+    scenes (paper_2606_09074_amd.serve) with the scenes in FP32, BF16/FP16
+    and FP16 storage, once more with FP32 scenes where every job runs the
+    whole path; then the same jobs as a burst (capacity, with and without
+    overlap and packing) and, with FP32 and FP16 scenes, Poisson arrivals at
+    70% of the burst capacity, where jobs overlap on the device.  Latency =
+    completion seen by the host - arrival time."""
     import numpy as np
     import torch
 
@@ -285,11 +442,12 @@ def serve_bench(args) -> dict:
     dev = torch.device("cuda:0")
     specs = synth.serve_scene_specs(8)
     log(f"serve: generating {len(specs)} resident scenes, n = {[sp.n for sp in specs]}")
-    f32, b16 = [], []
+    stores = {"f32": [], "bf16_f16": [], "f16": []}
     for sp in specs:
         pl = synth.make_planes(sp)
-        f32.append(torch.from_numpy(pl).to(dev))
-        b16.append(torch.from_numpy(synth.quantize_bf16_f16(pl)).to(dev))
+        stores["f32"].append(torch.from_numpy(pl).to(dev))
+        stores["bf16_f16"].append(torch.from_numpy(synth.quantize_bf16_f16(pl)).to(dev))
+        stores["f16"].append(torch.from_numpy(synth.quantize_f16(pl)).to(dev))
     arrivals, reqs = synth.serve_requests(args.serve_jobs, len(specs), rate=args.serve_rate)
     cams = {}
     for _, V, _ in reqs:
@@ -299,8 +457,9 @@ def serve_bench(args) -> dict:
 
     tuner = serve.Tuner()
     buckets = sorted({(serve.bucket_of(sp.n, V)) for sp in specs for V in (64, 128, 256)})
-    tuner.tune(f32[-1], lambda V: torch.from_numpy(synth.ring_cameras(V)).to(dev), buckets, reps=3)
-    log(f"serve: tuned {len(buckets)} buckets: {sorted(tuner.table.items())}")
+    tuner.tune(stores["f32"][-1], lambda V: torch.from_numpy(synth.ring_cameras(V)).to(dev), buckets, reps=3,
+               prepared=True)
+    log(f"serve: tuned {len(buckets)} buckets on prepared scenes: {sorted(tuner.table.items())}")
 
     def run(scenes, arr, slots, prepare=True, pack=True):
         srv = serve.Server(dev, slots=slots, tuner=tuner, prepare_scenes=prepare,
@@ -332,21 +491,31 @@ def serve_bench(args) -> dict:
                 "device_p99_ms": round(serve.percentile(dev_ms, 0.99), 3),
                 "jobs_per_s": round(len(fin) / span, 2), "evals_per_s": round(evals / span, 1)}, order
 
-    log(f"serve: {len(reqs)} jobs at {args.serve_rate}/s, FP32 scenes")
-    r32, k32 = run(f32, arrivals, args.serve_slots)
-    log(f"serve: same jobs, BF16/FP16 scenes")
-    r16, k16 = run(b16, arrivals, args.serve_slots)
-    log(f"serve: same jobs, FP32 scenes, every job on the whole path (no prepared scenes)")
-    r32u, _ = run(f32, arrivals, args.serve_slots, prepare=False)
-    jac = []
-    for a, b in zip(k32, k16):
-        a, b = a.bool(), b.bool()
-        jac.append(float((a & b).sum().item()) / max(float((a | b).sum().item()), 1.0))
+    def jaccard(ka, kb):
+        out = []
+        for a, b in zip(ka, kb):
+            a, b = a.bool(), b.bool()
+            out.append(float((a & b).sum().item()) / max(float((a | b).sum().item()), 1.0))
+        return {"min": round(min(out), 5), "mean": round(float(np.mean(out)), 5)}
+
+    res, keeps = {}, {}
+    for name in ("f32", "bf16_f16", "f16"):
+        log(f"serve: {len(reqs)} jobs at {args.serve_rate}/s, {name} scenes")
+        res[name], keeps[name] = run(stores[name], arrivals, args.serve_slots)
+    log("serve: same jobs, FP32 scenes, every job on the whole path (no prepared scenes)")
+    res["f32_whole_path"], _ = run(stores["f32"], arrivals, args.serve_slots, prepare=False)
     burst = np.zeros(len(reqs))
     log("serve: burst (all jobs at once), with and without overlap")
-    b4, _ = run(f32, burst, args.serve_slots)
-    b4n, _ = run(f32, burst, args.serve_slots, pack=False)
-    b1, _ = run(f32, burst, 1, pack=False)
+    b4, _ = run(stores["f32"], burst, args.serve_slots)
+    b4n, _ = run(stores["f32"], burst, args.serve_slots, pack=False)
+    b1, _ = run(stores["f32"], burst, 1, pack=False)
+    # Poisson arrivals at 70% of the burst capacity: jobs arrive while others
+    # are on the device and overlap there
+    busy_rate = round(0.7 * b4["jobs_per_s"], 1)
+    busy_arr, _ = synth.serve_requests(args.serve_jobs, len(specs), rate=busy_rate)
+    log(f"serve: same jobs at {busy_rate}/s (70% of the burst capacity), FP32 and FP16 scenes")
+    busy32, _ = run(stores["f32"], busy_arr, args.serve_slots)
+    busy16, _ = run(stores["f16"], busy_arr, args.serve_slots)
     # the same jobs on small resident scenes (20k..200k Gaussians), where
     # launches rather than arithmetic set the pace: packed vs one launch
     # sequence per job
@@ -355,11 +524,14 @@ def serve_bench(args) -> dict:
     log("serve: burst on small scenes, packed and unpacked")
     s4, _ = run(small, burst, args.serve_slots)
     s4n, _ = run(small, burst, args.serve_slots, pack=False)
-    return {"workload": "resident scenes n=0.25M..4.9M (log-uniform strata), 50..300 ring views, ratio 0.3..0.9",
+    return {"workload": f"8 resident scenes n=0.2M..6M (log-spaced, ends included), 50..300 ring views, "
+                        f"ratio 0.3..0.9, Poisson arrivals",
             "jobs": len(reqs), "rate_per_s": args.serve_rate, "slots": args.serve_slots,
             "latency_clock": "host: arrival to observed completion",
-            "f32": r32, "bf16_f16": r16, "f32_whole_path": r32u,
-            "kept_jaccard_bf16_vs_f32": {"min": round(min(jac), 5), "mean": round(float(np.mean(jac)), 5)},
+            **res,
+            "kept_jaccard_vs_f32": {"bf16_f16": jaccard(keeps["bf16_f16"], keeps["f32"]),
+                                    "f16": jaccard(keeps["f16"], keeps["f32"])},
+            "overlapping_load": {"rate_per_s": busy_rate, "f32": busy32, "f16": busy16},
             "burst": {"slots": args.serve_slots, "jobs_per_s": b4["jobs_per_s"], "evals_per_s": b4["evals_per_s"],
                       "unpacked_jobs_per_s": b4n["jobs_per_s"], "one_slot_unpacked_jobs_per_s": b1["jobs_per_s"]},
             "burst_small_scenes": {"n": "20k..200k", "packed_jobs_per_s": s4["jobs_per_s"],
