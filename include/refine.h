@@ -300,6 +300,9 @@ refine_status refine_select(const float* d_scores, int64_t n, double ratio, int6
                             void* d_ws, size_t ws_bytes, void* stream);
 
 /*
+ * The removal step of Sec. 3.3: the bottom beta*N primitives are removed
+ * permanently, so the pruned scene is the survivors of the keep mask (the
+ * paper's timings include saving them, Sec. 4.2 with Table 2).
  * Survivors of a keep mask, in their original order, all 59 planes
  * (bit copies): out->planes[p * out->stride + j] = in->planes[p * in->stride
  * + i_j] with i_j the j-th index whose d_keep is non-zero.  d_index_map

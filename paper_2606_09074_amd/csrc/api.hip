@@ -85,7 +85,7 @@ size_t workspace_layout(int64_t n, int32_t n_views, bool score, void* base, Work
     const size_t nt = (size_t)(num_tiles(n) > 0 ? num_tiles(n) : 1);
     const size_t nv = (size_t)(n_views > 0 ? n_views : 0);
     size_t off = 0;
-    const size_t o_sel = off;   off += align_up(sizeof(SelectState));
+    const size_t o_sel = off;   off += align_up(sizeof(SelectState) * kSelectStates);
     const size_t o_hist = off;  off += align_up(sizeof(uint32_t) * kSelectHistWords);
     const size_t o_part = off;  off += align_up(sizeof(double) * kStatSlots * nt);
     const size_t o_cnt = off;   off += align_up(sizeof(uint32_t) * nt);
@@ -146,7 +146,7 @@ constexpr int32_t kMaxBatchJobs = 4096;
 size_t batch_job_bytes(int64_t n, int32_t nv)
 {
     const size_t nt = (size_t)num_tiles(n);
-    return align_up(sizeof(SelectState)) + align_up(sizeof(uint32_t) * kSelectHistWords) +
+    return align_up(sizeof(SelectState) * kSelectStates) + align_up(sizeof(uint32_t) * kSelectHistWords) +
            align_up(sizeof(double) * kStatSlots * nt) + align_up(sizeof(uint32_t) * nt) +
            align_up(sizeof(uint32_t) * kSelectLastBins * nt) + align_up(sizeof(CamRec) * nv);
 }
@@ -442,7 +442,7 @@ refine_status refine_prune_batch(const refine_prune_job* jobs, int32_t n_jobs, c
         b.n_out = j.d_n_out;
         const size_t nt = (size_t)num_tiles(n);
         b.sel = reinterpret_cast<SelectState*>(base + off);
-        off += align_up(sizeof(SelectState));
+        off += align_up(sizeof(SelectState) * kSelectStates);
         b.hist = reinterpret_cast<uint32_t*>(base + off);
         off += align_up(sizeof(uint32_t) * kSelectHistWords);
         b.stat_part = reinterpret_cast<double*>(base + off);

@@ -43,7 +43,12 @@ constexpr int kCamRec = 32;        // floats per prepared camera record
 constexpr int kHistBits = 11;
 constexpr int kHistBins = 1 << kHistBits;
 constexpr int kHistCopies = 8;    // selection histogram copies: spreads the atomics on crowded bins
-constexpr int kSelectHistWords = 3 * kHistCopies * kHistBins;   // one set of copies per radix pass
+constexpr int kSuperWidth = 32;    // bins per super-bin of a pass's coarse histogram
+constexpr int kCoarseBins = kHistBins / kSuperWidth;   // 64
+// one pass: kHistCopies copies of the kHistBins bins, then kHistCopies copies of the coarse bins
+constexpr int kPassWords = kHistCopies * (kHistBins + kCoarseBins);
+constexpr int kSelectHistWords = 3 * kPassWords;   // one set per radix pass
+constexpr int kSelectStates = 4;   // selection state before pass 0, after passes 0, 1 and 2
 constexpr int kSelectLastBins = 1 << 10;   // digits of the last radix pass (its per-tile rows)
 constexpr int kStatSlots = 8;      // doubles per stats partial
 constexpr int kNoAllocStatTiles = REFINE_STATS_NOALLOC_MAX_N / kTile;   // tiles of refine_stats_noalloc
@@ -67,7 +72,8 @@ struct CamRec {
 };
 static_assert(sizeof(CamRec) == kCamRec * sizeof(float), "camera record size");
 
-// Device-resident state of one selection (lives in the workspace).
+// Device-resident state of one selection (lives in the workspace, one slot
+// per stage: kSelectStates consecutive records).
 struct SelectState {
     int64_t n;
     int64_t n_prune;
