@@ -466,9 +466,11 @@ def serve_bench(args) -> dict:
                            pack_max_n=(1 << 20) if pack else 0)
         for t in scenes:
             srv.add_scene(t)
-        # warm the allocator and the kernels on every scene
-        for j in range(len(scenes)):
-            srv.submit(j, cams[reqs[0][1]], 0.5)
+        # steady state: the kernels, and the caching allocator of every slot
+        # stream, warmed by one untimed burst of the same jobs (a server that
+        # has run for a while no longer grows its pools per job)
+        for sc, V, r in reqs:
+            srv.submit(sc, cams[V], r)
         srv.drain()
         keeps = {}
 

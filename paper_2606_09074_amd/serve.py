@@ -382,9 +382,10 @@ class Server:
         job.start_event = torch.cuda.Event(enable_timing=True)
         if job.on_prepared:
             st, pws, ss = self.prepared[job.scene]
-            # the camera table may have been written on another stream
+            # the camera table may have been written on another stream; the
+            # slot's own stream is idle (a slot is freed only once its last
+            # job's done event has completed), so nothing else is waited for
             ss.wait_stream(torch.cuda.current_stream(dev))
-            ss.wait_stream(s)          # this slot's previous job no longer reads its buffers
             job.start_event.record(ss)
             job.stats = st
             api.refine_score_cameras(planes, job.cams, pws, job.params, n=n, stream=ss)
