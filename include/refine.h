@@ -326,7 +326,8 @@ refine_status refine_compact(const refine_scene* in, const uint8_t* d_keep, cons
  * direct path: params->score_path and records_per_lane are not used; the
  * scores equal refine_score's bit for bit), refine_select at the job's ratio
  * and refine_compact -- the same results as those calls made job by job,
- * with 13 launches for the whole batch instead of ~15 per job.  For serving
+ * with 9 launches (and one table copy) for the whole batch instead of 11 per
+ * job.  For serving
  * loops that gather the small scenes that arrive together.
  *  jobs       host array of n_jobs descriptions, read during the call (the
  *             table is copied into the workspace with a host-to-device copy

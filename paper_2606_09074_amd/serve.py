@@ -26,7 +26,7 @@ from the job's own camera set.  The server
 * packs small scenes: when two or more small jobs (default parameters, at
   most ``pack_max_n`` primitives) wait at the head of the queue, up to
   ``max_pack`` of them go to one slot as one ``refine_prune_batch`` -- one
-  grouped launch per kernel (13 in all) for all of them, its job table
+  grouped launch per kernel (9 in all) for all of them, its job table
   copied from the slot's pinned staging buffer without blocking the host;
 * notices completions by polling an event recorded after each launch unit's
   last call, then frees the slot and the reservation and admits the next
