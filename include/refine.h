@@ -37,7 +37,7 @@ extern "C" {
 typedef enum {
     REFINE_OK = 0,
     REFINE_E_INVALID = -1,      /* a null pointer, negative size, out-of-domain value */
-    REFINE_E_UNSUPPORTED = -2,  /* well-formed but outside what this build handles */
+    REFINE_E_UNSUPPORTED = -2,  /* well-formed but outside what the library handles */
     REFINE_E_WORKSPACE = -3,    /* workspace missing or smaller than required */
     REFINE_E_HIP = -4           /* a HIP launch failed */
 } refine_status;

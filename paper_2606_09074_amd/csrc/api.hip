@@ -200,7 +200,7 @@ const char* refine_status_string(int32_t status)
     switch (status) {
     case REFINE_OK: return "REFINE_OK";
     case REFINE_E_INVALID: return "REFINE_E_INVALID: invalid argument";
-    case REFINE_E_UNSUPPORTED: return "REFINE_E_UNSUPPORTED: unsupported by this build";
+    case REFINE_E_UNSUPPORTED: return "REFINE_E_UNSUPPORTED: well-formed but outside what the library handles";
     case REFINE_E_WORKSPACE: return "REFINE_E_WORKSPACE: workspace missing or too small";
     case REFINE_E_HIP: return "REFINE_E_HIP: HIP launch failed";
     default: return "unknown refine_status";
