@@ -22,7 +22,9 @@
  *    call for scenes of up to n primitives and n_views cameras.  Calls that
  *    share a workspace must be ordered (same stream); calls on different
  *    streams need different workspaces.
- *  - No global mutable state: calls are re-entrant across streams.
+ *  - No global mutable state: calls are re-entrant across streams.  The one
+ *    exception is refine_stats_noalloc, whose fixed per-GPU array is shared
+ *    by all its calls on that GPU (see there).
  */
 #ifndef REFINE_H
 #define REFINE_H
@@ -327,8 +329,7 @@ refine_status refine_compact(const refine_scene* in, const uint8_t* d_keep, cons
  * scores equal refine_score's bit for bit), refine_select at the job's ratio
  * and refine_compact -- the same results as those calls made job by job,
  * with 9 launches (and one table copy) for the whole batch instead of 11 per
- * job.  For serving
- * loops that gather the small scenes that arrive together.
+ * job.  For serving loops that gather the small scenes that arrive together.
  *  jobs       host array of n_jobs descriptions, read during the call (the
  *             table is copied into the workspace with a host-to-device copy
  *             on `stream`); 1 <= n_jobs <= 4096
@@ -362,8 +363,10 @@ refine_status refine_prune_batch_workspace_size(const refine_prune_job* jobs, in
                                                 const refine_params* params, size_t* bytes);
 
 /*
- * h_staging (nullable): PINNED host memory (hipHostMalloc) of at least
- * n_jobs * REFINE_BATCH_STAGING_BYTES_PER_JOB bytes, owned by the caller.
+ * h_staging (nullable): PINNED host memory (hipHostMalloc) of
+ * staging_bytes >= n_jobs * REFINE_BATCH_STAGING_BYTES_PER_JOB bytes (else
+ * REFINE_E_WORKSPACE), aligned to 8 bytes (else REFINE_E_INVALID), owned by
+ * the caller; staging_bytes is ignored when h_staging is NULL.
  * The call writes the device job table there and copies it to the workspace
  * asynchronously on `stream`, so the caller must leave the buffer untouched
  * until the stream has passed this call (an event recorded after it has

@@ -396,6 +396,7 @@ refine_status refine_prune_batch_workspace_size(const refine_prune_job* jobs, in
 }
 
 static_assert(sizeof(BatchJob) <= REFINE_BATCH_STAGING_BYTES_PER_JOB, "staging bytes per job");
+static_assert(alignof(BatchJob) == 8, "the staging alignment the header states");
 
 refine_status refine_prune_batch(const refine_prune_job* jobs, int32_t n_jobs, const refine_params* params,
                                  void* d_ws, size_t ws_bytes, void* h_staging, size_t staging_bytes, void* stream)
