@@ -118,7 +118,7 @@ typedef struct {
  *           binned path only, never a change of results: 0 = the library's
  *           choice, 1 or 2 views evaluated per iteration of the view loop (two
  *           independent evaluations interleaved; each primitive's sum still
- *           adds the views in increasing order)
+ *           adds the views in the order of refine_score)
  *  waves_per_block
  *           binned path only, never a change of results: 0 = the library's
  *           choice (4), or 1, 2, 4 or 8 wave64s (primitive groups of 64 or
@@ -231,7 +231,11 @@ refine_status refine_stats_noalloc(const refine_scene* scene, const refine_param
  *   D_i = sum_k lambda^k G~_i^k * (1/|V|) sum_v g_i^v V_i P_i^v
  * with the visibility V_i and projection P_i^v of the selected modes and the
  * gate g_i^v (depth > z_near and the 3-sigma footprint of the projected
- * covariance overlapping the image).  FP32 arithmetic, views summed in order.
+ * covariance overlapping the image).  FP32 arithmetic; each primitive's
+ * views are summed in order within blocks of 64 and the block sums added in
+ * order, so the rounding error of the mean grows with 64 + n_views / 64 (to
+ * first order at most (66 + n_views / 64) * 2^-24 relative, about 1e-3 at
+ * the 2^20 views a call accepts).
  * params->score_path picks how the pairs are scheduled (results identical).
  *  d_cams    device float32 [n_views][18]: world-to-camera rotation R
  *            (row-major), translation t (p_cam = R p + t), fx, fy, cx, cy,

@@ -29,7 +29,8 @@
 //   projection term: COV (a + c)/(z^2 + eta) (1/sbar^2 applied in the
 //       epilogue, as 1/(9 sbar^2) with the kernels' 3 L), DEPTH
 //       1/(z^2 + eta) (Eq. 17), NONE 1
-// Views are accumulated in view order into one FP32 sum per primitive; the
+// Views are accumulated in view order within blocks of 64 (kViewBlock), the
+// block sums added in order into one FP32 total per primitive; the
 // epilogue forms D = (V K [/ sbar^2]) S / |V| (Eq. 20, then Eq. 7).  The
 // binned records hold V K [/ sbar^2], which does not depend on the cameras,
 // so a new camera set only needs new camera records (refine_score_cameras).
@@ -166,6 +167,13 @@ __global__ __launch_bounds__(kBlock) void camera_prep(const float* __restrict__ 
 }
 
 // Registers a lane keeps for one primitive across the view loop.
+// Each primitive's sum over views is blocked: views in order within a block
+// of 64 (one 64-bit mask word of the binned path), block sums added in
+// order, so the FP32 rounding error grows with 64 + n_views / 64 instead of
+// n_views.
+constexpr int kViewBlock = 64;
+static_assert(kViewBlock == 64, "a block is one 64-bit mask word");
+
 struct Prim {
     float mx, my, mz;
     float L00, L01, L02, L10, L11, L12, L20, L21, L22;
@@ -317,8 +325,16 @@ __device__ __forceinline__ void score_direct_body(const void* __restrict__ plane
     Prim p;
     float pre, smax;
     activate<ST>(planes, stride, i, p, pre, smax, st, PROJ, vis_alpha);
-    for (int v = 0; v < nv; ++v) eval_pair<PROJ>(cams[v], p, eta, z_near);
-    out[i] = pre * p.S / (float)nv;
+    // views summed in order within each block of kViewBlock, the block sums
+    // added in order (the binned path takes the same blocks: its mask words)
+    float total = 0.0f;
+    for (int v0 = 0; v0 < nv; v0 += kViewBlock) {
+        const int v1 = min(v0 + kViewBlock, nv);
+        for (int v = v0; v < v1; ++v) eval_pair<PROJ>(cams[v], p, eta, z_near);
+        total += p.S;
+        p.S = 0.0f;
+    }
+    out[i] = pre * total / (float)nv;
 }
 
 template <int PROJ, int ST>
@@ -690,6 +706,7 @@ __device__ __forceinline__ void load_cam(const float4* __restrict__ r, CamEval& 
 }
 
 constexpr int kViewChunk = 256;   // views staged in LDS at a time (20 KB)
+static_assert(kViewChunk % kViewBlock == 0, "chunks hold whole blocks");
 
 // Bounds of view-loop group G (PPL groups of kGroup records), merged from
 // the PPL bound records it covers: the union box, and a sphere about the
@@ -868,7 +885,7 @@ __global__ __launch_bounds__(kBlock) void place_groups(const uint32_t* __restric
 // lane l holds records l, l + 64, ... of it) and evaluates every view its
 // mask keeps, in increasing view order, for all its records; VPI = 2 takes
 // two kept views per iteration (two independent evaluation chains to
-// interleave; the sums still add the views in order).  A block is 1 to
+// interleave; the sums still add the views in the same order).  A block is 1 to
 // kMaxLoopWaves waves, which share one LDS copy of the camera table.
 constexpr int kMaxLoopWaves = 8;
 constexpr int kDefaultLoopWaves = 4;
@@ -890,7 +907,7 @@ __global__ __launch_bounds__(64 * kMaxLoopWaves) void score_binned(const PrimRec
     const int G = active ? min(max(__builtin_amdgcn_readfirstlane(order[w]), 0), ngroups - 1) : 0;
     const int g0 = G * kGroup * PPL;
     Prim p[PPL];
-    float pre[PPL], smax[PPL];
+    float pre[PPL], smax[PPL], total[PPL];
     int idx[PPL];
 #pragma unroll
     for (int k = 0; k < PPL; ++k) {
@@ -903,6 +920,7 @@ __global__ __launch_bounds__(64 * kMaxLoopWaves) void score_binned(const PrimRec
         p[k].L10 = r.L[3]; p[k].L11 = r.L[4]; p[k].L12 = r.L[5];
         p[k].L20 = r.L[6]; p[k].L21 = r.L[7]; p[k].L22 = r.L[8];
         p[k].S = 0.0f;
+        total[k] = 0.0f;
         pre[k] = r.pre;
         idx[k] = (active && j < n) ? r.idx : -1;
     }
@@ -919,7 +937,7 @@ __global__ __launch_bounds__(64 * kMaxLoopWaves) void score_binned(const PrimRec
         for (int t = threadIdx.x; t < cn * kStageVec; t += blockDim.x)
             table[t] = reinterpret_cast<const float4*>(cams + c0 + t / kStageVec)[t % kStageVec];
         __syncthreads();
-        for (int v0 = c0; v0 < c0 + cn; v0 += 64) {
+        for (int v0 = c0; v0 < c0 + cn; v0 += kViewBlock) {   // one mask word
             uint64_t m = active ? gm[v0 / 64] : 0ull;
             while (m != 0ull) {
                 const int b = __builtin_ctzll(m);
@@ -974,11 +992,18 @@ __global__ __launch_bounds__(64 * kMaxLoopWaves) void score_binned(const PrimRec
                     }
                 }
             }
+            // the word's sum (its kept views, in order; the others add +0)
+            // joins the total, as the direct path's block sums do
+#pragma unroll
+            for (int k = 0; k < PPL; ++k) {
+                total[k] += p[k].S;
+                p[k].S = 0.0f;
+            }
         }
     }
 #pragma unroll
     for (int k = 0; k < PPL; ++k)
-        if (idx[k] >= 0) out[idx[k]] = pre[k] * p[k].S / (float)nv;
+        if (idx[k] >= 0) out[idx[k]] = pre[k] * total[k] / (float)nv;
     if (evaluated && active && lane == 0) {
         const int valid = max(0, min(kGroup * PPL, n - g0));   // records of this group
         const int slot = G % kEvalSlots;   // spread: one address would serialise the waves

@@ -34,7 +34,8 @@ from the job's own camera set.  The server
 
 Each job's results do not depend on what runs beside it: the library's
 reductions have fixed orders (FP64 statistics summed per tile in a fixed
-order, per-primitive view sums in view order, integer selection), so a job
+order, per-primitive view sums in view order within 64-view blocks,
+integer selection), so a job
 gives bit-identical scores, mask and survivors alone and in the mix.
 
 ``Tuner`` picks, per (primitive count, view count) bucket, the execution

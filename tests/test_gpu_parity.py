@@ -14,7 +14,7 @@ import pytest
 from tests.gpu_common import (check_compact, check_mask_vs_oracle, check_scores, check_stats,
                               expected_keep_from_scores, gpu_params, log, oracle_all, oracle_params, run_gpu,
                               workload)
-from tests.helpers import camera, planes_from_prims, raw_prim
+from tests.helpers import camera, planes_from_prims, raw_prim, within_interval
 
 pytestmark = pytest.mark.gpu
 
@@ -402,6 +402,38 @@ def test_binned_view_masks_and_chunks(n, v, rec, vpi):
     if n >= 777 and vpi == 1:
         F, lam, D, lo, hi = oracle_all(sub, rig)
         check_scores(b["scores"], D, lo, hi, f"binned n={n} V={v} rec={rec}")
+
+
+def test_maximum_view_count():
+    """The largest camera set a call takes, 2^20 views (16384 mask words and
+    4096 LDS camera chunks per group), on 64 primitives: both paths
+    bit-identical and within the rounding bound of their FP32 view sums of
+    the oracle.  Each primitive's sum adds 64-view blocks in order, each block
+    summed in order, so to first order its relative error stays below
+    (64 + V/64 + 2) * 2^-24 (about 1e-3 here; a plain running sum would
+    allow V * 2^-24 = 6%).  The rig repeats the 16 ring cameras, so the
+    oracle's scores also equal its scores for the 16 cameras alone."""
+    planes, cams, _ = workload("small")
+    n, V = 64, 1 << 20
+    sub = np.ascontiguousarray(planes[:, :n])
+    rig = np.ascontiguousarray(np.tile(cams, (V // cams.shape[0], 1)))
+    assert rig.shape == (V, 18)
+    log(f"[max views] n={n} V={V}")
+    d, b = _paths(sub, rig)
+    np.testing.assert_array_equal(b["scores"].view(np.uint32), d["scores"].view(np.uint32))
+    F, lam, D, lo, hi = oracle_all(sub, rig)
+    D16 = oracle_all(sub, cams)[2]
+    # the oracle's own FP64 running sum over V views: within V * 2^-53
+    np.testing.assert_allclose(D, D16, rtol=V * 2.0 ** -53, atol=1e-300)
+    bound = (64 + V // 64 + 2) * 2.0 ** -24
+    ok = within_interval(d["scores"], lo, hi, rel=bound)
+    amb = lo != hi
+    live = (D > 0) & ~amb
+    rel = np.abs(d["scores"].astype(np.float64) - D)[live] / D[live]
+    log(f"[max views] {int(live.sum())} unambiguous nonzero scores, max rel error {rel.max():.2e} "
+        f"(bound {bound:.2e}); {int(amb.sum())} with intervals")
+    assert live.sum() >= 16
+    assert ok.all(), np.nonzero(~ok)[0]
 
 
 def test_binned_path_with_degenerate_and_nonfinite_inputs():
