@@ -165,6 +165,8 @@ def main() -> int:
     value = n * V / (ms_per_step / 1e3)
     avg = res["phases_ms"]
     log(f"bench: {ms_per_step:.3f} ms/step, phases {avg}")
+    cold_ms = run.cold(args.steps)
+    log(f"bench: {cold_ms:.3f} ms per prune after a 1 GiB cache flush")
     n_eval, n_screened = run.pair_counts()
 
     # roofline of the view loop (the dominant kernel, the only launch of
@@ -236,6 +238,8 @@ def main() -> int:
                        "records_per_lane": args.records_per_lane, "views_per_iteration": args.views_per_iteration,
                        "waves_per_block": args.waves_per_block, "ms_per_prune": round(ms_per_step, 4)},
             "phases_ms": {k: round(v, 4) for k, v in avg.items()},
+            "cold_cache": {"ms_per_prune": round(cold_ms, 4), "flush": "1 GiB read before each prune",
+                           "clock": "HIP events around the prune on its stream"},
             "roofline": roofline, "cpu_baseline": cpu, "precision": precision, "other_workloads": others,
             "serving": serving}
     print(json.dumps(line), flush=True)
@@ -335,6 +339,25 @@ class Pruner:
         avg["views"] = float(np.mean(views_ms))
         return {"ms_per_step": round((t1 - t0) * 1e3 / max(steps, 1), 4), "phases_ms": {k: round(v, 4) for k, v in avg.items()}}
 
+    def cold(self, steps) -> float:
+        """Mean time of a prune that starts with a cold last-level cache: a
+        1 GiB read (which evicts the 256 MB cache) precedes each prune, and
+        HIP events on the launch stream bracket the prune alone."""
+        import numpy as np
+        torch = self.torch
+        flush = torch.ones(1 << 28, dtype=torch.float32, device=self.planes.device)
+        ms = []
+        for _ in range(max(steps, 1)):
+            flush.sum()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(self.stream)
+            self.step()
+            b.record(self.stream)
+            torch.cuda.synchronize()
+            ms.append(a.elapsed_time(b))
+        del flush
+        return float(np.mean(ms))
+
     def pair_counts(self):
         """Pairs the view loop evaluated in full and pairs it screened out
         after their first step (culled pairs are in neither)."""
@@ -383,6 +406,18 @@ def cpu_model() -> str:
     return "unknown"
 
 
+def cpu_mhz() -> float | None:
+    """The first logical CPU's current clock from /proc/cpuinfo."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("cpu MHz"):
+                    return round(float(line.split(":", 1)[1]), 1)
+    except (OSError, ValueError):
+        pass
+    return None
+
+
 def cpu_baseline(spec, planes_np, cams_np, ratio):
     """The FP64 oracle as it stands, timed on the host: the whole prune of
     the workload on all its OpenMP threads, and one thread on a bounded
@@ -423,7 +458,8 @@ def cpu_baseline(spec, planes_np, cams_np, ratio):
         log(f"bench: single-thread oracle leg failed: {e}")
     cpu = {"value": round(n * V / tc, 1), "unit": "evals/s", "cores": oracle.num_threads(), "kind": "oracle",
            "sample": f"full {spec.name} prune (stats+score+select+compact), {tc:.2f} s",
-           "ms_per_prune": round(tc * 1e3, 1), "cpu_model": cpu_model(), "single_thread": single}
+           "ms_per_prune": round(tc * 1e3, 1), "cpu_model": cpu_model(), "cpu_mhz": cpu_mhz(),
+           "logical_cpus_visible": os.cpu_count(), "single_thread": single}
     return cpu, D
 
 
