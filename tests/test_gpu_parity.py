@@ -330,7 +330,12 @@ def _paths(planes, cams, n=None, **kw):
                                          ("medium", 400_000, {}), ("small", 9000, dict(records_per_lane=2)),
                                          ("medium", 400_000, dict(records_per_lane=2)),
                                          ("small", 9000, dict(records_per_lane=1, views_per_iteration=2)),
-                                         ("medium", 400_000, dict(records_per_lane=2, views_per_iteration=2))])
+                                         ("medium", 400_000, dict(records_per_lane=2, views_per_iteration=2)),
+                                         ("small", 9000, dict(waves_per_block=1)),
+                                         ("small", None, dict(records_per_lane=1, waves_per_block=2)),
+                                         ("medium", 400_000, dict(records_per_lane=2, waves_per_block=8)),
+                                         ("medium", 400_000, dict(records_per_lane=1, views_per_iteration=2,
+                                                                  waves_per_block=8))])
 def test_binned_and_direct_paths_bit_identical(name, n, mode):
     """Culling skips only (group, view) pairs whose every primitive is gated
     out, so the binned path must reproduce the direct path bit for bit."""
