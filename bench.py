@@ -36,8 +36,10 @@ if ROOT not in sys.path:
 # y/z 2, u and v 4, Jacobian 4, J R_v 18, (J R_v) L 30, a b c 15, largest
 # eigenvalue and radius 11, footprint box 4, projection term 6, accumulate 1
 # = 114 (the kernel's square-root-free gate executes a few less).  DEPTH
-# and NONE modes skip the covariance part.
-FLOP_PER_PAIR = {0: 114, 1: 25, 2: 22}
+# and NONE modes change only the projection term (1/(z^2 + eta): 1 FLOP
+# from the shared reciprocal; or 1): the gate still needs the projected
+# covariance for the footprint radius.
+FLOP_PER_PAIR = {0: 114, 1: 109, 2: 108}
 # a pair screened out after its first step: camera-space centre 18, d z 4, bound 1
 FLOP_PER_SCREENED_PAIR = 23
 BYTES_PER_PRIM = 14 * 4 + 4
@@ -216,6 +218,19 @@ def main() -> int:
             others[sp.name] = {"ms_per_prune": r["ms_per_step"], "ratio": sp.ratios[0],
                                "evals_per_s": round(sp.n * sp.n_views / (r["ms_per_step"] / 1e3), 1),
                                "phases_ms": r["phases_ms"]}
+            del pr
+            torch.cuda.empty_cache()
+        # the paper's own cost setting (Table B.1) on this workload: the
+        # depth-only projection term (Eq. 17) over 64 subsampled views
+        if args.workload == "medium" and args.storage == "f32":
+            pp = _lib.default_params()
+            pp.proj_mode, pp.n_sub_views = _lib.PROJ_DEPTH, 64
+            log("bench: paper configuration (depth-only term, 64 views)")
+            pr = Pruner(run.planes, run.cams, ratio, pp)
+            r = pr.time(args.steps, args.warmup)
+            others[f"{spec.name}-depth-64-views"] = {
+                "ms_per_prune": r["ms_per_step"], "ratio": ratio, "views_evaluated": 64,
+                "evals_per_s": round(n * 64 / (r["ms_per_step"] / 1e3), 1), "phases_ms": r["phases_ms"]}
             del pr
             torch.cuda.empty_cache()
 

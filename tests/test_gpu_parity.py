@@ -298,6 +298,29 @@ _ORACLE_CACHE = {}
 
 
 @pytest.mark.slow
+def test_paper_configuration_at_full_size():
+    """The paper's own cost setting (Table B.1): the depth-only projection
+    term of Eq. 17 over 64 subsampled views, on the 3M-primitive, 200-view
+    workload: every score against the oracle in the same mode, the mask at
+    beta 0.5 against the oracle's, and the binned path equal to the direct
+    one."""
+    import oracle
+    planes, cams, spec = workload("medium")
+    mode = dict(proj_mode=1, n_sub_views=64)
+    F, lam, D, lo, hi = oracle_all(planes, cams, **mode)
+    n_prune = oracle.n_prune(spec.n, 0.5)
+    r = run_gpu(planes, cams, ratio=0.5, params=gpu_params(**mode))
+    d = run_gpu(planes, cams, params=gpu_params(score_path=1, **mode))
+    np.testing.assert_array_equal(r["scores"].view(np.uint32), d["scores"].view(np.uint32))
+    check_stats(r["stats"], F, lam, "paper configuration", **mode)
+    summary = check_scores(r["scores"], D, lo, hi, "paper configuration scores")
+    assert summary["n_interval"] <= 1e-3 * spec.n
+    np.testing.assert_array_equal(r["keep"], expected_keep_from_scores(r["scores"], n_prune))
+    check_mask_vs_oracle(r["keep"], D, lo, hi, n_prune, "paper configuration mask")
+    check_compact(planes, spec.n, r)
+
+
+@pytest.mark.slow
 def test_large_workload_full_parity():
     """6M primitives x 300 views at beta 0.66: every score against the
     oracle, the mask against the oracle's (identical except borderline) and
