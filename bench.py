@@ -64,9 +64,11 @@ def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
 
-# Sources of the view-loop kernels: HBM traffic measured with rocprofv3
-# counters is reported only while these are unchanged.
-KERNEL_SOURCES = ("paper_2606_09074_amd/csrc/score.hip", "paper_2606_09074_amd/csrc/refine_internal.hpp")
+# Sources of the view-loop kernels and the build that compiles them: HBM
+# traffic measured with rocprofv3 counters is reported only while these are
+# unchanged.
+KERNEL_SOURCES = ("paper_2606_09074_amd/csrc/score.hip", "paper_2606_09074_amd/csrc/refine_internal.hpp",
+                  "paper_2606_09074_amd/build.py")
 
 
 def kernel_sources_sha256() -> str:
