@@ -17,7 +17,11 @@ What it measures, per scene:
   blocks, over the attribute groups geometry / opacity / colour
   (assumption 2, attribute orthogonality), as in the paper's Sec. 5.4;
 * Spearman rank correlations of the REFINE score D (Eq. 7, 20), in both
-  projection modes, and of an opacity-only ranking, with Q.
+  projection modes, and of an opacity-only ranking, with Q;
+* for each attribute group (geometry scales, colour, opacity) the exact
+  diagonal Gauss-Newton weight of Eq. 8 in activated units, from the
+  renderer's finite differences, and its Spearman correlation with REFINE's
+  weight w_i^k = lambda^k alpha_i S_i / |V| (Eq. 20).
 
 The image is multilinear in the opacities, so removing primitive i changes
 it by exactly -alpha_i dR/dalpha_i: Q_i = alpha_i^2 mean_v ||dR/dalpha_i||^2,
@@ -171,6 +175,50 @@ def jacobian(prims, caches, subset, h: float = 1e-4):
     return J
 
 
+def exact_group_weights(prims, caches, h: float = 1e-4) -> dict:
+    """The exact diagonal Gauss-Newton weight of each attribute group of
+    every primitive (Eq. 8 with the second derivative of the image error
+    replaced by J^T J): W_i^k = mean over views of the squared norm of the
+    image's derivative with respect to the group's activated attributes --
+    opacity alpha, DC colour c = 0.5 + C0 dc, scales s -- from central
+    finite differences in the storage parameters and the chain rule
+    (d/dalpha = d/dlogit / (alpha (1 - alpha)), d/dc = d/ddc / C0,
+    d/ds = d/dlog s / s)."""
+    n = len(prims)
+    params = {"gem": [3, 4, 5], "opa": [9], "col": [10, 11, 12]}
+    W = {k: np.zeros(n) for k in params}
+    for i, p in enumerate(prims):
+        alpha = 1.0 / (1.0 + math.exp(-p.logit))
+        s = np.exp(p.log_scale)
+        for k, ps in params.items():
+            for q in ps:
+                gp = p.perturbed(q, h).gaussian()
+                gm = p.perturbed(q, -h).gaussian()
+                d2 = np.mean([np.sum(((c.image(i, gp) - c.image(i, gm)) / (2 * h)) ** 2) for c in caches])
+                if k == "opa":
+                    d2 /= (alpha * (1.0 - alpha)) ** 2
+                elif k == "col":
+                    d2 /= SH_C0 ** 2
+                else:
+                    d2 /= s[q - 3] ** 2
+                W[k][i] += d2
+    return W
+
+
+def refine_group_weight(prims, D, lam):
+    """REFINE's weight w_i^k = lambda^k alpha_i S_i / |V| (Eq. 20) without
+    its constant lambda^k: D_i / K_i with K_i = sum_k lambda^k G~_i^k
+    (Eq. 7), from the oracle's scores."""
+    K = []
+    for p in prims:
+        s = np.exp(p.log_scale)
+        alpha = 1.0 / (1.0 + math.exp(-p.logit))
+        g_gem = max(s[0] * s[1], s[0] * s[2], s[1] * s[2])
+        g_col = float(np.linalg.norm(0.5 + SH_C0 * p.dc))
+        K.append(lam[0] * g_gem + lam[1] * g_col + lam[2] * alpha)
+    return np.asarray(D) / np.asarray(K)
+
+
 def gauss_newton(J):
     """H = mean over views of J_v^T J_v (Eq. 3, 5 up to the noise scale)."""
     return np.einsum("vpa,vpb->ab", J, J) / J.shape[0]
@@ -190,14 +238,15 @@ def der_attributes(H, m: int) -> float:
     return float(num / den)
 
 
-def refine_scores(prims, cam_rows, proj_mode: int = 0):
+def refine_scores(prims, cam_rows, proj_mode: int = 0, with_lambda: bool = False):
     import oracle
     prm = oracle.Params(eta=ETA, z_near=Z_NEAR, clamp_k=CLAMP_K, e_col=E_COL, e_opa=E_OPA, e_lngem=E_LNGEM,
                         proj_mode=proj_mode)
     planes = oracle_planes(prims)
     F = oracle.stats(planes, eta=prm.eta)
     lam = oracle.lam(F, prm)
-    return oracle.score(planes, cam_rows, lam, prm)[0]
+    D = oracle.score(planes, cam_rows, lam, prm)[0]
+    return (D, lam) if with_lambda else D
 
 
 def study(n: int = 40, V: int = 8, seed: int = 0, neighbourhoods: int = 1, k_nn: int = 10) -> dict:
@@ -205,13 +254,19 @@ def study(n: int = 40, V: int = 8, seed: int = 0, neighbourhoods: int = 1, k_nn:
     cam_rows, cams = make_cameras(V)
     caches = [ViewCache(prims, c) for c in cams]
     Q = removal_errors(prims, caches)
-    D_cov = refine_scores(prims, cam_rows, 0)
+    D_cov, lam = refine_scores(prims, cam_rows, 0, with_lambda=True)
     D_depth = refine_scores(prims, cam_rows, 1)
     alpha = np.array([1.0 / (1.0 + math.exp(-p.logit)) for p in prims])
     out = {"n": n, "views": V, "seed": seed,
            "spearman_D_cov_vs_removal": float(spearmanr(D_cov, Q)[0]),
            "spearman_D_depth_vs_removal": float(spearmanr(D_depth, Q)[0]),
            "spearman_opacity_vs_removal": float(spearmanr(alpha, Q)[0])}
+    # REFINE's per-group weight (the same ranking for every group: only the
+    # constant lambda^k differs) against each group's exact diagonal weight
+    w = refine_group_weight(prims, D_cov, lam)
+    W = exact_group_weights(prims, caches)
+    for k in ("gem", "col", "opa"):
+        out[f"spearman_w_vs_exact_diag_{k}"] = float(spearmanr(w, W[k])[0])
     # DER over k-nearest-neighbour sets (dense local regions)
     rng = np.random.default_rng(seed + 1)
     mus = np.stack([p.mu for p in prims])

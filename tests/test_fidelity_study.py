@@ -16,6 +16,25 @@ def test_study_small_scene():
     assert r["removal_identity_max_rel_err"] < 1e-5
     assert 0.0 < r["der_primitives"] <= 1.0 and 0.0 < r["der_attributes"] <= 1.0
     assert r["spearman_D_cov_vs_removal"] > 0.3
+    # REFINE's weight (alpha S / |V|) ranks like the exact diagonal weights of
+    # the scale and colour groups, which scale with alpha as it does
+    assert r["spearman_w_vs_exact_diag_gem"] > 0.3 and r["spearman_w_vs_exact_diag_col"] > 0.3
+    assert -1.0 <= r["spearman_w_vs_exact_diag_opa"] <= 1.0
+
+
+def test_exact_opacity_weight_is_the_removal_error_over_alpha_squared():
+    """Blending is multilinear in the opacities, so removing i changes the
+    image by exactly -alpha_i dR/dalpha_i: the exact opacity weight (from the
+    finite differences in the logit and the chain rule) is Q_i / alpha_i^2."""
+    prims = fd.make_scene(10, seed=4)
+    rows, cams = fd.make_cameras(3)
+    caches = [fd.ViewCache(prims, c) for c in cams]
+    W = fd.exact_group_weights(prims, caches)
+    Q = fd.removal_errors(prims, caches)
+    alpha = np.array([1.0 / (1.0 + math.exp(-p.logit)) for p in prims])
+    seen = Q > 1e-12
+    assert seen.sum() >= 5
+    np.testing.assert_allclose(W["opa"][seen], Q[seen] / alpha[seen] ** 2, rtol=1e-5)
 
 
 def test_der_is_one_for_separated_primitives():
